@@ -1,0 +1,164 @@
+"""Benchmark of the RK3 time step of the half-range LB Couette solver on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--workload NAME]
+
+A step is one TVD RK3 step (three stages, each a closure launch and a stage launch) of
+every instance of the batch; the batch is B independent seeded instances of one
+workload, resident in HBM before timing starts.  Prints one JSON line with the
+throughput in G (node x velocity) pair-updates per second, the roofline record of the
+dominant kernel (the stage kernel, timed with HIP events on the stream it runs on) and
+the oracle timed on the host cores on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+# the oracle baseline runs single-threaded; fix the BLAS pool before numpy loads
+os.environ.setdefault('OPENBLAS_NUM_THREADS', '1')
+os.environ.setdefault('OMP_NUM_THREADS_ORACLE', '1')
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+BYTES_PER_PAIR_STEP = 64   # algorithmic: stage 1 16 B, stages 2-3 24 B each (read F_in, F_l; write F_out)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=100)
+    ap.add_argument('--warmup', type=int, default=10)
+    ap.add_argument('--batch', type=int, default=256)
+    ap.add_argument('--workload', default='couette_shakhov_s256_v800')
+    ap.add_argument('--cells', type=int, default=0)
+    ap.add_argument('--waves', type=int, default=0)
+    ap.add_argument('--no-cpu', action='store_true')
+    ap.add_argument('--cpu-seconds', type=float, default=15.0)
+    return ap.parse_args()
+
+
+def make_solver(wl, batch, device):
+    import numpy as np
+    import torch
+    from paper_1702_01335_amd import hrlb, inputs
+    q = hrlb.Quadrature(wl['Qx'], wl['Qy'], wl['Qz'])
+    S = wl['S']
+    r = torch.empty((batch, S, q.V), dtype=torch.float64, device=device)
+    for b in range(batch):
+        r[b] = torch.from_numpy(inputs.perturbation(1000 + b, (S, q.V)))
+    params = [hrlb.make_params(**wl['params']) for _ in range(batch)]
+    solver = hrlb.Solver(q, S, wl['scheme'], params, device=device, perturb=r, eps=0.05)
+    del r
+    return q, solver
+
+
+def time_steps(solver, steps, warmup):
+    import torch
+    solver.step(warmup)
+    solver.synchronize()
+    torch.cuda.synchronize()
+    s = solver.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    solver.step(steps)
+    e1.record(s)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def cpu_baseline(wl, seconds):
+    """The oracle (numpy, FP64, single-threaded) on one instance of the workload for a
+    bounded number of steps; returns pair-updates per second."""
+    import numpy as np
+    from oracle import solver as sv
+    from paper_1702_01335_amd import inputs
+    p = sv.Params(Qx=wl['Qx'], Qy=wl['Qy'], Qz=wl['Qz'], S=wl['S'], scheme=wl['scheme'], **wl['params'])
+    m = sv.Model(p)
+    F = sv.seeded_state(m, inputs.perturbation(1000, (p.S, m.V)), 0.05)
+    F = sv.rk3_step(F, m)  # warm-up
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds or n < 2:
+        F = sv.rk3_step(F, m)
+        n += 1
+    dt = time.perf_counter() - t0
+    return dict(value=p.S * m.V * n / dt / 1e9, unit='G pair-updates/s', cores=1, kind='oracle',
+                sample=f"{n} RK3 steps of one instance (S={p.S}, V={m.V}) in {dt:.1f} s, numpy single thread")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({'error': 'this build runs on one GPU only; multi-GPU runs are not part of it',
+                          'n_gpus': args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_1702_01335_amd.workloads import workload
+    wl = workload(args.workload)
+    device = 'cuda:0'
+    torch.cuda.set_device(0)
+    q, solver = make_solver(wl, args.batch, device)
+    if args.cells or args.waves:
+        c0, w0 = solver.get_launch()
+        solver.set_launch(args.cells or c0, args.waves or w0)
+    cells, waves = solver.get_launch()
+    pairs = args.batch * wl['S'] * q.V
+    ms, wall = time_steps(solver, args.steps, args.warmup)
+    value = pairs / (ms * 1e-3) / 1e9
+
+    # per-kernel device time of the same step sequence, HIP events on the solver's stream
+    solver.set_timing(True)
+    solver.step(min(args.steps, 20))
+    tm = solver.get_timing()
+    solver.set_timing(False)
+    stage_avg_s = tm['stage_ms'] / tm['stage_launches'] * 1e-3
+    closure_avg_s = tm['closure_ms'] / tm['closure_launches'] * 1e-3
+    bytes_per_launch = pairs * BYTES_PER_PAIR_STEP / 3.0
+    achieved = bytes_per_launch / stage_avg_s
+    res = solver.residual()
+
+    # single instance of the same workload (latency-bound; reported for context)
+    q1, s1 = make_solver(wl, 1, device)
+    ms1, _ = time_steps(s1, max(args.steps, 50), args.warmup)
+    single = dict(batch=1, ms_per_step=ms1, value=wl['S'] * q1.V / (ms1 * 1e-3) / 1e9)
+    del s1
+
+    out = {
+        'metric': 'G cell-velocity pair-updates/s per RK3 step (% HBM peak)',
+        'value': value,
+        'unit': 'G pair-updates/s',
+        'n_gpus': 1,
+        'steps': args.steps,
+        'warmup': args.warmup,
+        'ms_per_step': ms,
+        'higher_is_better': True,
+        'scaling': 'weak',
+        'vs_baseline': None,
+        'dtype': 'f64',
+        'data': 'synthetic',
+        'config': {'workload': f"{args.workload} x {args.batch} independent seeded instances",
+                   'batch': args.batch, 'S': wl['S'], 'V': q.V, 'Qx': wl['Qx'], 'Qy': wl['Qy'], 'Qz': wl['Qz'],
+                   'scheme': wl['scheme'], 'pairs': pairs, 'launch': {'cells': cells, 'waves': waves},
+                   'parallelism': 'single GPU'},
+        'hbm_frac_step': pairs * BYTES_PER_PAIR_STEP / (ms * 1e-3) / HBM_PEAK,
+        'roofline': {'bound': 'hbm', 'achieved': achieved / 1e9, 'peak': HBM_PEAK / 1e9, 'unit': 'GB/s',
+                     'frac': achieved / HBM_PEAK, 'traffic': None,
+                     'kernel': 'stage_kernel', 'avg_launch_us': stage_avg_s * 1e6,
+                     'bytes_per_launch': bytes_per_launch, 'closure_avg_us': closure_avg_s * 1e6},
+        'single_instance': single,
+        'residual_max': float(res.max()),
+        'wall_s_timed': wall,
+    }
+    if not args.no_cpu:
+        out['cpu_baseline'] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == '__main__':
+    main()

@@ -1,0 +1,171 @@
+/*
+ * hrlb.h -- C ABI of libhrlb, the MI355X (gfx950) time step of the mixed-quadrature
+ * lattice Boltzmann solver for 3D Couette flow of Ambrus & Sofonea, "Half-range lattice
+ * Boltzmann models for the simulation of Couette flow using the Shakhov collision term"
+ * (arXiv:1702.01335).
+ *
+ * Problem (Sec. III): plates at x = -L/2 and x = +L/2 (L = 1) move with -u_w and +u_w
+ * along y and are kept at T_w; by the centre-line symmetry the solver holds the half
+ * channel 0 <= x <= L/2 in S nodes (App. A.4), with bounce-back at x = 0 and diffuse
+ * reflection at x = L/2.  The velocity set is the product of a half-range Gauss-Hermite
+ * rule on x (2 Qx nodes) and full-range rules on y (Qy) and z (Qz): V = 2 Qx Qy Qz
+ * discrete velocities, flat index v = (i Qy + j) Qz + k, nodes ascending on each axis.
+ * Collision: Shakhov (BGK when Pr = 1), Eq. boltz, with the Hermite-projected
+ * equilibrium of Sec. III and tau from a power-law or Sutherland viscosity.  Space: WENO-5
+ * (App. A.3) or second-order upwind on the tanh-stretched grid (App. A.2).  Time: TVD RK3
+ * (App. A.1).
+ *
+ * Conventions
+ *  - Every function returns HRLB_OK (0) or a negative status; nothing throws or aborts.
+ *    hrlb_last_error() gives a message for the calling thread's last failure.
+ *  - Device memory is owned by the caller.  The library keeps raw pointers into the
+ *    caller's state and work buffers for the lifetime of an hrlb_sim and never frees them.
+ *    Host handles (hrlb_quad, hrlb_sim) are owned by the library and released by the
+ *    matching *_free call.
+ *  - All device work is enqueued on the caller's HIP stream (hipStream_t passed as void*;
+ *    NULL = the null stream).  Only hrlb_residual synchronises that stream.
+ *  - Population arrays are FP64, layout [B][S][V] (instance, node, velocity), v fastest.
+ */
+#ifndef HRLB_H
+#define HRLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HRLB_OK 0
+#define HRLB_EINVAL (-1)   /* invalid argument (sizes, parameters, null pointers)        */
+#define HRLB_ENOMEM (-2)   /* caller buffer smaller than hrlb_state_bytes requires        */
+#define HRLB_EHIP (-3)     /* a HIP runtime call failed; message holds hipGetErrorString  */
+#define HRLB_ENUMERIC (-4) /* n <= 0, T <= 0 or a non-finite moment met during a step     */
+
+#define HRLB_LAW_POWER 0      /* mu = kn T^omega  -> tau = kn T^(omega-1) / n  (Eq. mw_tau for omega = 1) */
+#define HRLB_LAW_SUTHERLAND 1 /* mu = kn sqrt(T)(1+S)/(1+S/T) -> Eq. sutherland_tau with kn = 1/(delta sqrt 2) */
+
+#define HRLB_SCHEME_UPWIND2 0 /* second-order upwind fluxes                                  */
+#define HRLB_SCHEME_WENO5 1   /* epsilon-free WENO-5, Eqs. weno5_flux..weno_sigma, Table II  */
+
+/* Physical and numerical parameters of one Couette instance (non-dimensional, Sec. II.B). */
+typedef struct hrlb_params {
+  double kn;       /* rarefaction: mu(T = 1) = kn, i.e. Kn of Sec. V, 1/(delta sqrt 2) of Sec. VI; > 0 */
+  double u_w;      /* wall speed; the wall at x = +L/2 moves with +u_w along y                       */
+  double T_w;      /* wall temperature (> 0)                                                          */
+  double n0;       /* initial density of the equilibrium start (> 0)                                 */
+  double pr;       /* Prandtl number of the Shakhov model (> 0); 1 = BGK                              */
+  double omega;    /* viscosity index of HRLB_LAW_POWER                                               */
+  double suth_S;   /* Sutherland constant S / T_ref of HRLB_LAW_SUTHERLAND (>= 0)                      */
+  double A;        /* tanh stretching of Eq. stretch, 0 <= A < 1; 0 = equidistant nodes               */
+  double dt;       /* time step (> 0)                                                                 */
+  int law;         /* HRLB_LAW_*                                                                      */
+  int collisionless; /* nonzero: drop the collision term (1/tau = 0)                                 */
+} hrlb_params;
+
+typedef struct hrlb_quad hrlb_quad;
+typedef struct hrlb_sim hrlb_sim;
+
+/* Message for the calling thread's last failed call ("" if none). Owned by the library. */
+const char* hrlb_last_error(void);
+
+/*
+ * init_quadrature -- host-side velocity set and Hermite projection tables (Sec. III:
+ * HHLB(Nx;Qx) x HLB(Ny;Qy), here with a third full-range factor HLB(Nz;Qz) on z).
+ *   Qx: nodes per x semi-axis, 1..128; Nx: half-range expansion order, 0..min(Qx-1, 8)
+ *   (the paper uses Nx = min(6, Qx-1)).  Qy, Qz: full-range nodes, 1..16; Ny <= Qy-1,
+ *   Nz <= Qz-1 (the paper uses N = Q-1).  No device work.
+ *   Errors: HRLB_EINVAL on out-of-range orders or out == NULL.
+ */
+int hrlb_init_quadrature(int Qx, int Nx, int Qy, int Ny, int Qz, int Nz, hrlb_quad** out);
+void hrlb_quad_free(hrlb_quad* q);
+
+/* Number of discrete velocities V = 2 Qx Qy Qz. */
+int hrlb_quad_size(const hrlb_quad* q, int* V);
+
+/*
+ * Nodes and weights of one axis (0 = x: 2 Qx values, ascending, weights summing to 1;
+ * 1 = y: Qy values; 2 = z: Qz values).  Host buffers of the axis' length.
+ */
+int hrlb_quad_nodes(const hrlb_quad* q, int axis, double* nodes, double* weights);
+
+/*
+ * state_bytes -- device bytes the caller allocates for `batch` instances of S nodes:
+ *   *state_bytes: three population arrays [batch][S][V] (the step's F_l and two RK
+ *                 stage buffers); *work_bytes: tables, moment partials, per-node closure,
+ *                 wall densities, residual partials and fault flags.
+ * Both buffers must be 256-byte aligned (torch allocations are).
+ */
+int hrlb_state_bytes(const hrlb_quad* q, int S, int batch, size_t* state_bytes, size_t* work_bytes);
+
+/*
+ * init_state -- bind buffers and write the initial state of `batch` instances that
+ * share the velocity set `q`, the node count S (>= 3) and the flux scheme.
+ *   params[b]: per-instance parameters (host array of `batch` entries).
+ *   d_state, d_work: caller device buffers of at least the hrlb_state_bytes sizes.
+ *   stream: hipStream_t all work of this sim is enqueued on.
+ *   d_perturb: NULL, or a device array r[batch][S][V]; the initial state is
+ *     F = n0 F^eq(u = 0, T = T_w) (1 + eps r) with F^eq the discrete equilibrium at rest.
+ *     (The paper does not state its initial condition; equilibrium at rest is the
+ *     library's reading.)
+ * The quadrature handle must outlive the sim.
+ * Errors: HRLB_EINVAL (S < 3, batch < 1, dt <= 0, kn <= 0, T_w <= 0, n0 <= 0, pr <= 0,
+ *   A outside [0, 1), unknown law or scheme), HRLB_ENOMEM (buffers too small), HRLB_EHIP.
+ */
+int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* params, int batch,
+                    void* d_state, size_t state_bytes, void* d_work, size_t work_bytes, void* stream,
+                    const double* d_perturb, double eps, hrlb_sim** out);
+void hrlb_sim_free(hrlb_sim* sim);
+
+/*
+ * step -- enqueue `nsteps` TVD RK3 steps (Eq. rk3) of every instance.  Each stage
+ * rebuilds the ghost nodes and the wall density from its own input (App. A.4), takes the
+ * moments of Eq. qdef, the relaxation time and the Shakhov target (Eqs. phieq, sdef) and
+ * advances F by L[F] of Eq. L_def.  Asynchronous; a numerical fault surfaces at the next
+ * hrlb_residual.  Errors: HRLB_EINVAL (nsteps < 0), HRLB_EHIP.
+ */
+int hrlb_step(hrlb_sim* sim, int nsteps);
+
+/*
+ * moments -- enqueue the per-node moments of the current state (Eq. qdef, m = 1) into
+ * the device array d_out[batch][S][14]: n, u_x, u_y, u_z, T, P_xx, P_yy, P_zz, P_xy,
+ * P_xz, P_yz, q_x, q_y, q_z (P_ab is the paper's pressure tensor T_ij, T = tr P / 3n).
+ */
+int hrlb_moments(hrlb_sim* sim, double* d_out);
+
+/*
+ * residual -- synchronise the stream and write to the host array h_out[batch] the
+ * residual of the last completed step, R = ||F_{l+1} - F_l||_2 / (dt ||F_l||_2) over the
+ * fluid nodes (a relative rate per unit time; the paper leaves the stopping rule open).
+ * Returns HRLB_ENUMERIC if any instance met n <= 0, T <= 0 or a non-finite moment since
+ * init (h_out is still written; the flags stay set).  Before any step h_out is 0.
+ */
+int hrlb_residual(hrlb_sim* sim, double* h_out);
+
+/* Copy the current state (interior nodes, [batch][S][V]) to / from a caller device array
+ * (enqueued on the sim's stream).  set_state also recomputes the moment partials. */
+int hrlb_get_state(hrlb_sim* sim, double* d_out);
+int hrlb_set_state(hrlb_sim* sim, const double* d_in);
+
+/*
+ * Launch shape of the stage kernel: `cells` nodes marched per thread (1..32; 0 = the
+ * library's default) and `waves` 64-lane waves per workgroup along v (1..16).  Any shape
+ * gives the same result up to the summation order of the moment partials.
+ */
+int hrlb_set_launch(hrlb_sim* sim, int cells, int waves);
+int hrlb_get_launch(const hrlb_sim* sim, int* cells, int* waves);
+
+/*
+ * Optional per-kernel timing: when on, hrlb_step brackets every launch with HIP events on
+ * the sim's stream; hrlb_get_timing synchronises and returns the accumulated device time
+ * in ms and launch counts of [0] the stage kernel, [1] the closure kernel.  Turning it on
+ * resets the accumulators.
+ */
+int hrlb_set_timing(hrlb_sim* sim, int on);
+int hrlb_get_timing(hrlb_sim* sim, double* ms, long long* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRLB_H */

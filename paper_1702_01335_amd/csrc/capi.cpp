@@ -1,0 +1,474 @@
+// C ABI of libhrlb (declared in include/hrlb.h): argument checking, buffer carve-up,
+// table upload and the launch sequence of the RK3 step.  Host code only; all device work
+// is enqueued on the caller's stream.
+#include "hrlb.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hrlb_internal.h"
+
+using namespace hrlb;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(HRLB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)            \
+  do {                                 \
+    hipError_t _e = (expr);            \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct hrlb_quad {
+  QuadTables t;
+};
+
+struct hrlb_sim {
+  Shape sh;
+  DevPtrs d;
+  WorkLayout lay;
+  hipStream_t stream;
+  int cells, waves;
+  int part_nvb;      // nvb of the launch that produced the current moment partials
+  int resid_nres;    // residual partial count of the last stage-3 launch (0: none yet)
+  bool timing;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop), kind in ev_kind
+  std::vector<int> ev_kind;
+  double ms[2];
+  long long launches[2];
+};
+
+namespace hrlb {
+
+WorkLayout work_layout(const Shape& sh) {
+  WorkLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const size_t dsz = sizeof(double);
+  L.nvb_max = (sh.V + 63) / 64;
+  L.nres_max = L.nvb_max * sh.S;
+  L.px = take(2 * sh.Qx * dsz);
+  L.py = take(sh.Qy * dsz);
+  L.pz = take(sh.Qz * dsz);
+  L.phix = take((size_t)sh.Qx * (sh.Nx + 1) * dsz);
+  L.cx = take((size_t)(sh.Nx + 1) * (sh.Nx + 1) * dsz);
+  L.phiy = take((size_t)sh.Qy * (sh.Ny + 1) * dsz);
+  L.phiz = take((size_t)sh.Qz * (sh.Nz + 1) * dsz);
+  L.inst = take((size_t)sh.B * sizeof(InstDev));
+  L.inv_dx = take((size_t)sh.B * sh.S * dsz);
+  L.g_rest = take((size_t)sh.B * sh.V * dsz);
+  L.g_wall = take((size_t)sh.B * sh.V * dsz);
+  L.partials = take((size_t)sh.B * L.nvb_max * sh.S * PART_STRIDE * dsz);
+  L.rec = take((size_t)sh.B * sh.S * sh.rec_len * dsz);
+  L.nw = take((size_t)sh.B * dsz);
+  L.resid_part = take((size_t)sh.B * L.nres_max * 2 * dsz);
+  L.resid = take((size_t)sh.B * dsz);
+  L.flags = take((size_t)sh.B * sizeof(int));
+  L.total = off;
+  return L;
+}
+
+}  // namespace hrlb
+
+static Shape make_shape(const QuadTables& t, int S, int B, int scheme) {
+  Shape sh;
+  sh.Qx = t.Qx;
+  sh.Nx = t.Nx;
+  sh.Qy = t.Qy;
+  sh.Ny = t.Ny;
+  sh.Qz = t.Qz;
+  sh.Nz = t.Nz;
+  sh.QyQz = t.Qy * t.Qz;
+  sh.V = 2 * t.Qx * sh.QyQz;
+  sh.S = S;
+  sh.B = B;
+  sh.scheme = scheme;
+  int rl = REC_HEAD + 2 * t.Qx + sh.QyQz;
+  sh.rec_len = (rl + 1) & ~1;
+  return sh;
+}
+
+// Node positions of App. A.2 (Eqs. stretch, etas), 1-based fractional index s.
+static double node_x(double s, int S, double A) {
+  if (A == 0.0) return (s - 0.5) / (2.0 * S);
+  const double eta = (s - 0.5) * std::atanh(A) / S;
+  return std::tanh(eta) / (2.0 * A);
+}
+
+static int default_cells(const Shape& sh) {
+  // enough node chunks to fill the device for one instance, long marches for batches
+  const long long pairs = (long long)sh.B * sh.S * sh.V;
+  if (pairs >= (1LL << 24)) return 16;
+  if (pairs >= (1LL << 21)) return 8;
+  return 4;
+}
+
+static int default_waves(const Shape& sh) {
+  const int wv = (sh.V + 63) / 64;
+  // smallest waves-per-block in 4..16 that wastes the fewest lanes
+  int best = 4, best_waste = 1 << 30;
+  for (int w = 4; w <= 16; ++w) {
+    const int nvb = (wv + w - 1) / w;
+    const int waste = nvb * w - wv;
+    if (waste < best_waste) {
+      best = w;
+      best_waste = waste;
+    }
+  }
+  return std::min(best, std::max(1, wv));
+}
+
+extern "C" {
+
+const char* hrlb_last_error(void) { return g_err.c_str(); }
+
+int hrlb_init_quadrature(int Qx, int Nx, int Qy, int Ny, int Qz, int Nz, hrlb_quad** out) {
+  if (!out) return fail(HRLB_EINVAL, "init_quadrature: out is NULL");
+  *out = nullptr;
+  if (Qx < 1 || Qx > QX_MAX) return fail(HRLB_EINVAL, "init_quadrature: Qx must be in 1..128");
+  if (Nx < 0 || Nx > std::min(Qx - 1, NX_MAX)) return fail(HRLB_EINVAL, "init_quadrature: need 0 <= Nx <= min(Qx-1, 8)");
+  if (Qy < 1 || Qy > QYZ_MAX || Qz < 1 || Qz > QYZ_MAX) return fail(HRLB_EINVAL, "init_quadrature: Qy, Qz must be in 1..16");
+  if (Ny < 0 || Ny > Qy - 1 || Nz < 0 || Nz > Qz - 1)
+    return fail(HRLB_EINVAL, "init_quadrature: need 0 <= Ny <= Qy-1 and 0 <= Nz <= Qz-1");
+  hrlb_quad* q = new hrlb_quad;
+  build_quadrature(Qx, Nx, Qy, Ny, Qz, Nz, q->t);
+  *out = q;
+  return HRLB_OK;
+}
+
+void hrlb_quad_free(hrlb_quad* q) { delete q; }
+
+int hrlb_quad_size(const hrlb_quad* q, int* V) {
+  if (!q || !V) return fail(HRLB_EINVAL, "quad_size: NULL argument");
+  *V = 2 * q->t.Qx * q->t.Qy * q->t.Qz;
+  return HRLB_OK;
+}
+
+int hrlb_quad_nodes(const hrlb_quad* q, int axis, double* nodes, double* weights) {
+  if (!q || !nodes || !weights) return fail(HRLB_EINVAL, "quad_nodes: NULL argument");
+  const std::vector<double>*p, *w;
+  if (axis == 0) {
+    p = &q->t.px;
+    w = &q->t.wx;
+  } else if (axis == 1) {
+    p = &q->t.py;
+    w = &q->t.wy;
+  } else if (axis == 2) {
+    p = &q->t.pz;
+    w = &q->t.wz;
+  } else {
+    return fail(HRLB_EINVAL, "quad_nodes: axis must be 0, 1 or 2");
+  }
+  std::memcpy(nodes, p->data(), p->size() * sizeof(double));
+  std::memcpy(weights, w->data(), w->size() * sizeof(double));
+  return HRLB_OK;
+}
+
+int hrlb_state_bytes(const hrlb_quad* q, int S, int batch, size_t* state_bytes, size_t* work_bytes) {
+  if (!q || !state_bytes || !work_bytes) return fail(HRLB_EINVAL, "state_bytes: NULL argument");
+  if (S < 3 || batch < 1) return fail(HRLB_EINVAL, "state_bytes: need S >= 3 and batch >= 1");
+  const Shape sh = make_shape(q->t, S, batch, 0);
+  *state_bytes = 3 * align256((size_t)batch * S * sh.V * sizeof(double));
+  *work_bytes = work_layout(sh).total;
+  return HRLB_OK;
+}
+
+int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* params, int batch, void* d_state,
+                    size_t state_bytes, void* d_work, size_t work_bytes, void* stream, const double* d_perturb,
+                    double eps, hrlb_sim** out) {
+  if (!out) return fail(HRLB_EINVAL, "init_state: out is NULL");
+  *out = nullptr;
+  if (!q || !params || !d_state || !d_work) return fail(HRLB_EINVAL, "init_state: NULL argument");
+  if (S < 3) return fail(HRLB_EINVAL, "init_state: S must be >= 3 (three ghost layers mirror nodes 1..3)");
+  if (batch < 1) return fail(HRLB_EINVAL, "init_state: batch must be >= 1");
+  if (scheme != HRLB_SCHEME_UPWIND2 && scheme != HRLB_SCHEME_WENO5) return fail(HRLB_EINVAL, "init_state: unknown scheme");
+  if (((uintptr_t)d_state & 255) || ((uintptr_t)d_work & 255))
+    return fail(HRLB_EINVAL, "init_state: buffers must be 256-byte aligned");
+  for (int b = 0; b < batch; ++b) {
+    const hrlb_params& p = params[b];
+    const std::string at = " (instance " + std::to_string(b) + ")";
+    if (!(p.dt > 0) || !std::isfinite(p.dt)) return fail(HRLB_EINVAL, "init_state: dt must be > 0" + at);
+    if (!(p.kn > 0) || !std::isfinite(p.kn)) return fail(HRLB_EINVAL, "init_state: kn must be > 0" + at);
+    if (!(p.T_w > 0)) return fail(HRLB_EINVAL, "init_state: T_w must be > 0" + at);
+    if (!(p.n0 > 0)) return fail(HRLB_EINVAL, "init_state: n0 must be > 0" + at);
+    if (!(p.pr > 0)) return fail(HRLB_EINVAL, "init_state: pr must be > 0" + at);
+    if (!(p.A >= 0 && p.A < 1)) return fail(HRLB_EINVAL, "init_state: A must be in [0, 1)" + at);
+    if (p.law != HRLB_LAW_POWER && p.law != HRLB_LAW_SUTHERLAND) return fail(HRLB_EINVAL, "init_state: unknown law" + at);
+    if (p.law == HRLB_LAW_SUTHERLAND && !(p.suth_S >= 0)) return fail(HRLB_EINVAL, "init_state: suth_S must be >= 0" + at);
+    if (!std::isfinite(p.u_w) || !std::isfinite(p.omega)) return fail(HRLB_EINVAL, "init_state: non-finite u_w/omega" + at);
+  }
+  const Shape sh = make_shape(q->t, S, batch, scheme);
+  const WorkLayout L = work_layout(sh);
+  const size_t arr = align256((size_t)batch * S * sh.V * sizeof(double));
+  if (state_bytes < 3 * arr) return fail(HRLB_ENOMEM, "init_state: state buffer smaller than hrlb_state_bytes");
+  if (work_bytes < L.total) return fail(HRLB_ENOMEM, "init_state: work buffer smaller than hrlb_state_bytes");
+
+  hrlb_sim* s = new hrlb_sim;
+  s->sh = sh;
+  s->lay = L;
+  s->stream = (hipStream_t)stream;
+  s->cells = default_cells(sh);
+  s->waves = default_waves(sh);
+  s->part_nvb = 0;
+  s->resid_nres = 0;
+  s->timing = false;
+  s->ms[0] = s->ms[1] = 0;
+  s->launches[0] = s->launches[1] = 0;
+  char* w = (char*)d_work;
+  DevPtrs& d = s->d;
+  d.px = (const double*)(w + L.px);
+  d.py = (const double*)(w + L.py);
+  d.pz = (const double*)(w + L.pz);
+  d.phix = (const double*)(w + L.phix);
+  d.cx = (const double*)(w + L.cx);
+  d.phiy = (const double*)(w + L.phiy);
+  d.phiz = (const double*)(w + L.phiz);
+  d.inst = (InstDev*)(w + L.inst);
+  d.inv_dx = (double*)(w + L.inv_dx);
+  d.g_rest = (double*)(w + L.g_rest);
+  d.g_wall = (double*)(w + L.g_wall);
+  d.partials = (double*)(w + L.partials);
+  d.rec = (double*)(w + L.rec);
+  d.nw = (double*)(w + L.nw);
+  d.resid_part = (double*)(w + L.resid_part);
+  d.resid = (double*)(w + L.resid);
+  d.flags = (int*)(w + L.flags);
+  for (int k = 0; k < 3; ++k) d.F[k] = (double*)((char*)d_state + k * arr);
+
+  // host-side per-instance tables
+  std::vector<InstDev> inst(batch);
+  std::vector<double> invdx((size_t)batch * S);
+  for (int b = 0; b < batch; ++b) {
+    const hrlb_params& p = params[b];
+    InstDev& I = inst[b];
+    std::memset(&I, 0, sizeof(I));
+    I.dt = p.dt;
+    I.kn = p.kn;
+    I.omega = p.omega;
+    I.suth = p.suth_S;
+    I.pr = p.pr;
+    I.n0 = p.n0;
+    I.T_w = p.T_w;
+    I.u_w = p.u_w;
+    I.law = p.law;
+    I.collisionless = p.collisionless ? 1.0 : 0.0;
+    // Lagrange weights of App. A.4: node S+1 from S, S-1, S-2 and node S+2 from S+1, S, S-1 (1-based)
+    for (int g = 0; g < 2; ++g) {
+      const double xs = node_x(S + 1 + g, S, p.A);
+      const double x1 = node_x(S + g, S, p.A), x2 = node_x(S - 1 + g, S, p.A), x3 = node_x(S - 2 + g, S, p.A);
+      I.ex[3 * g + 0] = (xs - x2) * (xs - x3) / ((x1 - x2) * (x1 - x3));
+      I.ex[3 * g + 1] = (xs - x1) * (xs - x3) / ((x2 - x1) * (x2 - x3));
+      I.ex[3 * g + 2] = (xs - x1) * (xs - x2) / ((x3 - x1) * (x3 - x2));
+    }
+    for (int c = 0; c < S; ++c) {
+      const double dx = node_x(c + 1.5, S, p.A) - node_x(c + 0.5, S, p.A);
+      invdx[(size_t)b * S + c] = 1.0 / dx;
+    }
+  }
+  hipStream_t st = s->stream;
+  const QuadTables& t = q->t;
+  auto up = [&](const void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = up(d.px, t.px.data(), t.px.size() * sizeof(double));
+  if (e == hipSuccess) e = up(d.py, t.py.data(), t.py.size() * sizeof(double));
+  if (e == hipSuccess) e = up(d.pz, t.pz.data(), t.pz.size() * sizeof(double));
+  if (e == hipSuccess) e = up(d.phix, t.phix.data(), t.phix.size() * sizeof(double));
+  if (e == hipSuccess) e = up(d.cx, t.cx.data(), t.cx.size() * sizeof(double));
+  if (e == hipSuccess) e = up(d.phiy, t.phiy.data(), t.phiy.size() * sizeof(double));
+  if (e == hipSuccess) e = up(d.phiz, t.phiz.data(), t.phiz.size() * sizeof(double));
+  if (e == hipSuccess) e = up(d.inst, inst.data(), inst.size() * sizeof(InstDev));
+  if (e == hipSuccess) e = up(d.inv_dx, invdx.data(), invdx.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMemsetAsync(d.flags, 0, batch * sizeof(int), st);
+  if (e == hipSuccess) e = hipMemsetAsync(d.resid, 0, batch * sizeof(double), st);
+  // the host vectors above must stay alive until the copies complete
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "init_state: table upload");
+  }
+  if ((e = (hipError_t)launch_setup_tables(sh, d, st)) != hipSuccess ||
+      (e = (hipError_t)launch_init_state(sh, d, d_perturb, eps, st)) != hipSuccess ||
+      (e = (hipError_t)launch_partials(sh, d, d.F[0], s->cells, s->waves, st)) != hipSuccess) {
+    delete s;
+    return hip_fail(e, "init_state: launch");
+  }
+  s->part_nvb = (sh.V + 64 * s->waves - 1) / (64 * s->waves);
+  *out = s;
+  return HRLB_OK;
+}
+
+void hrlb_sim_free(hrlb_sim* s) {
+  if (!s) return;
+  for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  delete s;
+}
+
+static hipError_t ev_begin(hrlb_sim* s, hipEvent_t* e0) {
+  if (!s->timing) return hipSuccess;
+  hipError_t e = hipEventCreate(e0);
+  if (e == hipSuccess) e = hipEventRecord(*e0, s->stream);
+  return e;
+}
+
+static hipError_t ev_end(hrlb_sim* s, hipEvent_t e0, int kind) {
+  if (!s->timing) return hipSuccess;
+  hipEvent_t e1;
+  hipError_t e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+  if (e == hipSuccess) {
+    s->ev.push_back(e0);
+    s->ev.push_back(e1);
+    s->ev_kind.push_back(kind);
+  }
+  return e;
+}
+
+int hrlb_step(hrlb_sim* s, int nsteps) {
+  if (!s) return fail(HRLB_EINVAL, "step: sim is NULL");
+  if (nsteps < 0) return fail(HRLB_EINVAL, "step: nsteps must be >= 0");
+  const Shape& sh = s->sh;
+  DevPtrs& d = s->d;
+  const int nvb = (sh.V + 64 * s->waves - 1) / (64 * s->waves);
+  const int nch = (sh.S + s->cells - 1) / s->cells;
+  for (int n = 0; n < nsteps; ++n) {
+    for (int stage = 1; stage <= 3; ++stage) {
+      const double* Fin = d.F[stage - 1];
+      double* Fout = d.F[stage % 3];  // stage 1 -> F[1], 2 -> F[2], 3 -> F[0] (in place over F_l)
+      hipEvent_t e0 = nullptr;
+      hipError_t e = ev_begin(s, &e0);
+      if (e == hipSuccess) e = (hipError_t)launch_closure(sh, d, Fin, s->part_nvb, nullptr, s->stream);
+      if (e == hipSuccess) e = ev_end(s, e0, 1);
+      if (e == hipSuccess) e = ev_begin(s, &e0);
+      if (e == hipSuccess)
+        e = (hipError_t)launch_stage(sh, d, stage, Fin, d.F[0], Fout, s->cells, s->waves, s->stream);
+      if (e == hipSuccess) e = ev_end(s, e0, 0);
+      if (e != hipSuccess) return hip_fail(e, "step: launch");
+      s->part_nvb = nvb;
+    }
+    s->resid_nres = nvb * nch;
+  }
+  return HRLB_OK;
+}
+
+int hrlb_moments(hrlb_sim* s, double* d_out) {
+  if (!s || !d_out) return fail(HRLB_EINVAL, "moments: NULL argument");
+  hipError_t e = (hipError_t)launch_partials(s->sh, s->d, s->d.F[0], s->cells, s->waves, s->stream);
+  if (e == hipSuccess) {
+    s->part_nvb = (s->sh.V + 64 * s->waves - 1) / (64 * s->waves);
+    e = (hipError_t)launch_closure(s->sh, s->d, s->d.F[0], s->part_nvb, d_out, s->stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "moments: launch");
+  return HRLB_OK;
+}
+
+int hrlb_residual(hrlb_sim* s, double* h_out) {
+  if (!s || !h_out) return fail(HRLB_EINVAL, "residual: NULL argument");
+  const int B = s->sh.B;
+  if (s->resid_nres > 0) {
+    hipError_t e = (hipError_t)launch_residual(s->sh, s->d, s->resid_nres, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "residual: launch");
+  }
+  std::vector<int> flags(B);
+  HIP_TRY(hipMemcpyAsync(h_out, s->d.resid, B * sizeof(double), hipMemcpyDeviceToHost, s->stream), "residual: copy");
+  HIP_TRY(hipMemcpyAsync(flags.data(), s->d.flags, B * sizeof(int), hipMemcpyDeviceToHost, s->stream), "residual: copy");
+  HIP_TRY(hipStreamSynchronize(s->stream), "residual: synchronize");
+  for (int b = 0; b < B; ++b)
+    if (flags[b]) return fail(HRLB_ENUMERIC, "residual: instance " + std::to_string(b) + " met n <= 0, T <= 0 or a non-finite moment");
+  return HRLB_OK;
+}
+
+int hrlb_get_state(hrlb_sim* s, double* d_out) {
+  if (!s || !d_out) return fail(HRLB_EINVAL, "get_state: NULL argument");
+  const size_t bytes = (size_t)s->sh.B * s->sh.S * s->sh.V * sizeof(double);
+  HIP_TRY(hipMemcpyAsync(d_out, s->d.F[0], bytes, hipMemcpyDeviceToDevice, s->stream), "get_state: copy");
+  return HRLB_OK;
+}
+
+int hrlb_set_state(hrlb_sim* s, const double* d_in) {
+  if (!s || !d_in) return fail(HRLB_EINVAL, "set_state: NULL argument");
+  const size_t bytes = (size_t)s->sh.B * s->sh.S * s->sh.V * sizeof(double);
+  HIP_TRY(hipMemcpyAsync(s->d.F[0], d_in, bytes, hipMemcpyDeviceToDevice, s->stream), "set_state: copy");
+  hipError_t e = (hipError_t)launch_partials(s->sh, s->d, s->d.F[0], s->cells, s->waves, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "set_state: launch");
+  s->part_nvb = (s->sh.V + 64 * s->waves - 1) / (64 * s->waves);
+  s->resid_nres = 0;
+  return HRLB_OK;
+}
+
+int hrlb_set_launch(hrlb_sim* s, int cells, int waves) {
+  if (!s) return fail(HRLB_EINVAL, "set_launch: sim is NULL");
+  if (cells == 0) cells = default_cells(s->sh);
+  if (cells != 1 && cells != 2 && cells != 4 && cells != 8 && cells != 16 && cells != 32)
+    return fail(HRLB_EINVAL, "set_launch: cells must be 1, 2, 4, 8, 16 or 32");
+  if (waves < 1 || waves > 16) return fail(HRLB_EINVAL, "set_launch: waves must be in 1..16");
+  // the partials in flight keep their own block count (part_nvb)
+  s->cells = cells;
+  s->waves = waves;
+  return HRLB_OK;
+}
+
+int hrlb_get_launch(const hrlb_sim* s, int* cells, int* waves) {
+  if (!s || !cells || !waves) return fail(HRLB_EINVAL, "get_launch: NULL argument");
+  *cells = s->cells;
+  *waves = s->waves;
+  return HRLB_OK;
+}
+
+int hrlb_set_timing(hrlb_sim* s, int on) {
+  if (!s) return fail(HRLB_EINVAL, "set_timing: sim is NULL");
+  HIP_TRY(hipStreamSynchronize(s->stream), "set_timing: synchronize");
+  for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  s->ev.clear();
+  s->ev_kind.clear();
+  s->ms[0] = s->ms[1] = 0;
+  s->launches[0] = s->launches[1] = 0;
+  s->timing = on != 0;
+  return HRLB_OK;
+}
+
+int hrlb_get_timing(hrlb_sim* s, double* ms, long long* launches) {
+  if (!s || !ms || !launches) return fail(HRLB_EINVAL, "get_timing: NULL argument");
+  HIP_TRY(hipStreamSynchronize(s->stream), "get_timing: synchronize");
+  for (size_t k = 0; k < s->ev_kind.size(); ++k) {
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, s->ev[2 * k], s->ev[2 * k + 1]), "get_timing: elapsed");
+    s->ms[s->ev_kind[k]] += t;
+    s->launches[s->ev_kind[k]] += 1;
+    (void)hipEventDestroy(s->ev[2 * k]);
+    (void)hipEventDestroy(s->ev[2 * k + 1]);
+  }
+  s->ev.clear();
+  s->ev_kind.clear();
+  ms[0] = s->ms[0];
+  ms[1] = s->ms[1];
+  launches[0] = s->launches[0];
+  launches[1] = s->launches[1];
+  return HRLB_OK;
+}
+
+}  // extern "C"

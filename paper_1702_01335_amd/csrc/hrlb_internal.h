@@ -1,0 +1,94 @@
+// Internal declarations shared by the host C ABI (capi.cpp), the host quadrature
+// (quadrature.cpp) and the device kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace hrlb {
+
+constexpr int NX_MAX = 8;    // largest half-range expansion order on x
+constexpr int NYZ_MAX = 15;  // largest full-range expansion order on y, z (Q <= 16)
+constexpr int QYZ_MAX = 16;
+constexpr int QX_MAX = 128;
+constexpr int REC_HEAD = 16;  // scalars at the head of a per-node closure record
+constexpr int PART_STRIDE = 16;  // doubles per (block, node) moment partial (13 used)
+constexpr int NMOM = 13;
+
+// Host quadrature tables (double, rounded from long double).
+struct QuadTables {
+  int Qx, Nx, Qy, Ny, Qz, Nz;
+  std::vector<double> px, wx;    // 2 Qx, ascending
+  std::vector<double> py, wy;    // Qy
+  std::vector<double> pz, wz;    // Qz
+  std::vector<double> phix;      // [Qx][Nx+1]: w_m h_l(p_m) / gamma_l, positive nodes m
+  std::vector<double> cx;        // [Nx+1][Nx+1]: monomial coefficients of monic h_l
+  std::vector<double> phiy;      // [Qy][Ny+1]: w_j He_l(p_j) / l!
+  std::vector<double> phiz;      // [Qz][Nz+1]
+};
+
+int build_quadrature(int Qx, int Nx, int Qy, int Ny, int Qz, int Nz, QuadTables& qt);
+
+// Per-instance constants on the device (doubles, fixed layout).
+struct InstDev {
+  double dt, kn, omega, suth, pr, n0, T_w, u_w;
+  double wall_den;   // sum_{p_x<0} p_x F^eq_w / n_w   (filled on the device)
+  double ex[6];      // Lagrange weights: ghost S from S-1,S-2,S-3 and ghost S+1 from S,S-1,S-2 (0-based)
+  double law;        // 0 power, 1 Sutherland
+  double collisionless;
+  double pad;
+};
+static_assert(sizeof(InstDev) == 18 * 8, "InstDev layout");
+
+// Device pointers of a sim (all carved out of the caller's work and state buffers).
+struct DevPtrs {
+  // velocity set tables
+  const double* px;   // [2Qx]
+  const double* py;   // [Qy]
+  const double* pz;   // [Qz]
+  const double* phix; // [Qx][Nx+1]
+  const double* cx;   // [Nx+1][Nx+1]
+  const double* phiy; // [Qy][Ny+1]
+  const double* phiz; // [Qz][Nz+1]
+  // per instance
+  InstDev* inst;      // [B]
+  double* inv_dx;     // [B][S]
+  double* g_rest;     // [B][V]  discrete equilibrium at rest per unit density
+  double* g_wall;     // [B][V]  wall Maxwellian per unit density
+  // per step / stage
+  double* partials;   // [B][nvb][S][PART_STRIDE]
+  double* rec;        // [B][S][rec_len]
+  double* nw;         // [B]
+  double* resid_part; // [B][nres][2]
+  double* resid;      // [B]
+  int* flags;         // [B]
+  // populations
+  double* F[3];       // three [B][S][V] arrays
+};
+
+struct Shape {
+  int Qx, Nx, Qy, Ny, Qz, Nz;
+  int V, QyQz, S, B;
+  int scheme;
+  int rec_len;        // REC_HEAD + 2 Qx + Qy Qz, rounded up to even
+};
+
+// Work-buffer carve-up; returns the total bytes and fills offsets.
+struct WorkLayout {
+  size_t px, py, pz, phix, cx, phiy, phiz, inst, inv_dx, g_rest, g_wall, partials, rec, nw, resid_part,
+      resid, flags, total;
+  int nvb_max, nres_max;
+};
+WorkLayout work_layout(const Shape& sh);
+
+// Kernel launchers (kernels.hip).  Every launcher returns a hipError_t cast to int.
+int launch_setup_tables(const Shape& sh, const DevPtrs& d, void* stream);
+int launch_init_state(const Shape& sh, const DevPtrs& d, const double* perturb, double eps, void* stream);
+int launch_partials(const Shape& sh, const DevPtrs& d, const double* F, int cells, int waves, void* stream);
+int launch_closure(const Shape& sh, const DevPtrs& d, const double* Fin, int nvb, double* mom_out, void* stream);
+int launch_stage(const Shape& sh, const DevPtrs& d, int stage, const double* Fin, const double* Fl, double* Fout,
+                 int cells, int waves, void* stream);
+int launch_residual(const Shape& sh, const DevPtrs& d, int nres, void* stream);
+
+}  // namespace hrlb

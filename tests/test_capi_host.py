@@ -1,0 +1,114 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every symbol
+include/hrlb.h declares, builds velocity sets that match the oracle's independently
+constructed Gauss rules, and rejects invalid arguments before touching device memory."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import quadrature as oq
+from paper_1702_01335_amd import hrlb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, 'include', 'hrlb.h')).read()
+    return sorted(set(re.findall(r'\b(hrlb_[a-z_]+)\s*\(', src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hrlb.load()
+    names = declared_symbols()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(hrlb.EXPORTS)
+
+
+@pytest.mark.parametrize("Qx", [1, 2, 4, 7, 16, 32, 50, 100, 128])
+def test_half_range_rule_matches_oracle(Qx):
+    q = hrlb.Quadrature(Qx, 4, 5)
+    p, w = q.nodes(0)
+    po, wo = oq.x_axis(Qx)
+    assert np.all(np.abs(p / po - 1) <= 4e-16)
+    assert np.all(np.abs(w / wo - 1) <= 1e-15)
+    assert np.array_equal(p, -p[::-1]) and np.array_equal(w, w[::-1])
+
+
+@pytest.mark.parametrize("Q", [1, 2, 3, 4, 5, 6, 7, 12, 16])
+def test_full_range_rule_matches_oracle(Q):
+    q = hrlb.Quadrature(2, Q, Q)
+    for axis in (1, 2):
+        p, w = q.nodes(axis)
+        po, wo = oq.full_range_rule(Q)
+        assert np.allclose(p, po, rtol=0, atol=4e-16 * max(1, np.abs(po).max()))
+        assert np.allclose(w, wo, rtol=1e-15, atol=0)
+        assert np.array_equal(p, -p[::-1])
+
+
+def test_velocity_count():
+    assert hrlb.Quadrature(16, 5, 5).V == 800
+    assert hrlb.Quadrature(50, 6, 6).V == 3600
+
+
+@pytest.mark.parametrize("args", [(0, 0, 4, 3, 4, 3), (129, 6, 4, 3, 4, 3), (4, 4, 4, 3, 4, 3), (8, 9, 4, 3, 4, 3),
+                                  (4, 3, 4, 4, 4, 3), (4, 3, 17, 3, 4, 3), (4, 3, 4, 3, 4, -1)])
+def test_init_quadrature_rejects_bad_orders(args):
+    with pytest.raises(hrlb.HrlbError) as e:
+        hrlb.init_quadrature(*args)
+    assert e.value.code == hrlb.HRLB_EINVAL
+
+
+def test_state_bytes():
+    q = hrlb.Quadrature(4, 4, 4)
+    sb, wb = hrlb.state_bytes(q.handle, 64, 2)
+    assert sb >= 3 * 2 * 64 * 128 * 8 and wb > 0
+    with pytest.raises(hrlb.HrlbError):
+        hrlb.state_bytes(q.handle, 2, 1)
+
+
+class FakeBuf:
+    """Stands in for a device tensor: init_state validates arguments before any device use."""
+
+    def __init__(self, ptr, n):
+        self.ptr, self.n = ptr, n
+
+    def data_ptr(self):
+        return self.ptr
+
+    def numel(self):
+        return self.n
+
+
+@pytest.mark.parametrize("bad", [dict(dt=0.0), dict(kn=-1.0), dict(T_w=0.0), dict(n0=0.0), dict(pr=0.0), dict(A=1.0),
+                                 dict(A=-0.1), dict(law=7), dict(dt=float('nan'))])
+def test_init_state_rejects_bad_parameters(bad):
+    q = hrlb.Quadrature(4, 4, 4)
+    sb, wb = hrlb.state_bytes(q.handle, 8, 1)
+    kw = dict(kn=0.1, dt=1e-3)
+    kw.update(bad)
+    p = hrlb.make_params(**kw)
+    with pytest.raises(hrlb.HrlbError) as e:
+        hrlb.init_state(q.handle, 8, 0, [p], FakeBuf(1 << 20, sb), FakeBuf(1 << 30, wb), 0)
+    assert e.value.code == hrlb.HRLB_EINVAL
+
+
+def test_init_state_rejects_small_buffers_and_bad_shapes():
+    q = hrlb.Quadrature(4, 4, 4)
+    sb, wb = hrlb.state_bytes(q.handle, 8, 1)
+    p = hrlb.make_params(kn=0.1, dt=1e-3)
+    with pytest.raises(hrlb.HrlbError) as e:
+        hrlb.init_state(q.handle, 8, 0, [p], FakeBuf(1 << 20, sb - 8), FakeBuf(1 << 30, wb), 0)
+    assert e.value.code == hrlb.HRLB_ENOMEM
+    with pytest.raises(hrlb.HrlbError) as e:
+        hrlb.init_state(q.handle, 2, 0, [p], FakeBuf(1 << 20, sb), FakeBuf(1 << 30, wb), 0)
+    assert e.value.code == hrlb.HRLB_EINVAL
+    with pytest.raises(hrlb.HrlbError) as e:
+        hrlb.init_state(q.handle, 8, 5, [p], FakeBuf(1 << 20, sb), FakeBuf(1 << 30, wb), 0)
+    assert e.value.code == hrlb.HRLB_EINVAL
+    with pytest.raises(hrlb.HrlbError) as e:   # misaligned
+        hrlb.init_state(q.handle, 8, 0, [p], FakeBuf((1 << 20) + 8, sb), FakeBuf(1 << 30, wb), 0)
+    assert e.value.code == hrlb.HRLB_EINVAL

@@ -1,0 +1,124 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on the same
+seeded inputs, element by element (tolerances derived in tests/parity.py)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import solver as sv
+from paper_1702_01335_amd.workloads import workload
+
+from parity import assert_parity, gpu_run, make_wl, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+# small shapes that still span several blocks and chunks and end in ragged tails:
+# V = 90 (one full wave plus 26 lanes), S = 13 (not a multiple of the chunk)
+SMALL = [
+    ('weno5-shakhov-stretched', make_wl(5, 3, 3, 13, 'weno5', A=0.9, dt=1e-4)),
+    ('upwind2-bgk', make_wl(5, 3, 3, 13, 'upwind2', pr=1.0, omega=1.0)),
+    ('weno5-sutherland', make_wl(4, 5, 3, 11, 'weno5', law='sutherland', suth_S=0.5239, kn=0.05, u_w=1.0)),
+    ('weno5-collisionless', make_wl(6, 4, 2, 9, 'weno5', collisionless=True, u_w=0.5)),
+]
+
+
+@pytest.mark.parametrize("label,wl", SMALL, ids=[s[0] for s in SMALL])
+def test_small_shapes_default_launch(label, wl):
+    Fg, mom, res, _ = gpu_run(wl, 5, seeds=[7])
+    Fo, m, Ro = oracle_run(wl, 5, seed=7)
+    assert_parity(Fg[0], Fo, m, label)
+    assert res[0] == pytest.approx(Ro, rel=1e-9)
+
+
+@pytest.mark.parametrize("cells", [1, 2, 4, 8, 16, 32])
+@pytest.mark.parametrize("waves", [1, 2, 3, 16])
+def test_launch_shapes_agree_with_oracle(cells, waves):
+    wl = SMALL[0][1]
+    Fg, _, _, _ = gpu_run(wl, 3, seeds=[11], launch=(cells, waves))
+    Fo, m, _ = oracle_run(wl, 3, seed=11)
+    assert_parity(Fg[0], Fo, m, f"cells={cells} waves={waves}")
+
+
+def test_moments_match_oracle():
+    wl = SMALL[0][1]
+    Fg, mom, _, _ = gpu_run(wl, 4, seeds=[5])
+    Fo, m, _ = oracle_run(wl, 4, seed=5)
+    ref = sv.moments(Fo, m).table()
+    scale = np.abs(ref).max(axis=0)
+    scale = np.maximum(scale, 1e-12)
+    assert np.all(np.abs(mom[0] - ref) <= 1e-11 * scale)
+
+
+def test_batch_of_different_instances():
+    """Instances of one batch differ in every per-instance parameter; each must match its
+    own oracle run."""
+    base = make_wl(5, 3, 3, 12, 'weno5')
+    plist = [
+        dict(base['params']),
+        dict(base['params'], kn=1.5, u_w=0.6, A=0.95, dt=5e-5),
+        dict(base['params'], law='sutherland', suth_S=0.3101, kn=0.07, pr=2 / 3),
+        dict(base['params'], pr=1.0, omega=1.0, T_w=1.3, n0=0.8),
+        dict(base['params'], collisionless=True, u_w=0.2),
+    ]
+    Fg, _, res, _ = gpu_run(base, 4, seeds=[21, 22, 23, 24, 25], params_list=plist)
+    for b, p in enumerate(plist):
+        Fo, m, Ro = oracle_run(base, 4, seed=21 + b, params=p)
+        assert_parity(Fg[b], Fo, m, f"instance {b}")
+        assert res[b] == pytest.approx(Ro, rel=1e-9)
+
+
+@pytest.mark.parametrize("steps", [1, 10, 60])
+def test_bgk_s64_v128_full_size(steps):
+    wl = workload('couette_bgk_s64_v128')
+    Fg, _, res, _ = gpu_run(wl, steps, seeds=[1])
+    Fo, m, Ro = oracle_run(wl, steps, seed=1)
+    assert_parity(Fg[0], Fo, m, f"bgk s64 v128 steps={steps}")
+    assert res[0] == pytest.approx(Ro, rel=1e-8)
+
+
+@pytest.mark.parametrize("steps", [1, 10])
+def test_shakhov_s256_v800_full_size(steps):
+    wl = workload('couette_shakhov_s256_v800')
+    Fg, _, res, _ = gpu_run(wl, steps, seeds=[2])
+    Fo, m, Ro = oracle_run(wl, steps, seed=2)
+    assert_parity(Fg[0], Fo, m, f"shakhov s256 v800 steps={steps}")
+    assert res[0] == pytest.approx(Ro, rel=1e-8)
+
+
+def test_shakhov_s512_v3600_full_size():
+    wl = workload('couette_shakhov_s512_v3600')
+    Fg, _, res, _ = gpu_run(wl, 2, seeds=[3])
+    Fo, m, Ro = oracle_run(wl, 2, seed=3)
+    assert_parity(Fg[0], Fo, m, "shakhov s512 v3600 steps=2")
+    assert res[0] == pytest.approx(Ro, rel=1e-8)
+
+
+def test_gas_at_rest_on_gpu():
+    wl = make_wl(6, 5, 5, 20, 'weno5', u_w=0.0, A=0.98, dt=1e-4)
+    Fg, mom, res, solver = gpu_run(wl, 200)
+    Fo, m, _ = oracle_run(wl, 0)
+    assert np.abs(Fg[0] - Fo).max() / Fo.max() < 1e-13
+    assert np.abs(mom[0][:, 1:4]).max() < 1e-14
+
+
+def test_mass_conservation_on_gpu():
+    wl = make_wl(6, 4, 4, 24, 'weno5', u_w=0.5, A=0.9, dt=5e-5)
+    m = sv.Model(__import__('parity').oracle_params(wl))
+    F0, _, _, solver = gpu_run(wl, 0, seeds=[9])
+    mass0 = math.fsum((m.dx[:, None] * F0[0]).ravel())
+    solver.step(300)
+    F = solver.get_state().cpu().numpy()[0]
+    assert math.fsum((m.dx[:, None] * F).ravel()) == pytest.approx(mass0, rel=1e-13)
+
+
+def test_numeric_fault_is_reported():
+    import torch
+    wl = make_wl(4, 3, 3, 8, 'upwind2')
+    _, _, _, solver = gpu_run(wl, 1)
+    F = solver.get_state()
+    F[0, 3, :] = float('nan')
+    solver.set_state(F)
+    solver.step(1)
+    rc, _ = solver.residual(raise_on_fault=False)
+    assert rc == -4
