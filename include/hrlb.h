@@ -148,9 +148,9 @@ int hrlb_get_state(hrlb_sim* sim, double* d_out);
 int hrlb_set_state(hrlb_sim* sim, const double* d_in);
 
 /*
- * Launch shape of the stage kernel: `cells` nodes marched per thread (1..32; 0 = the
- * library's default) and `waves` 64-lane waves per workgroup along v (1..16).  Any shape
- * gives the same result up to the summation order of the moment partials.
+ * Launch shape of the stage kernel: `cells` nodes marched per thread (1..4096; 0 = the
+ * library's default) and `waves` 64-lane waves per workgroup along v (1..4; 0 = default).
+ * Any shape gives the same result up to the summation order of the moment partials.
  */
 int hrlb_set_launch(hrlb_sim* sim, int cells, int waves);
 int hrlb_get_launch(const hrlb_sim* sim, int* cells, int* waves);

@@ -77,6 +77,7 @@ WorkLayout work_layout(const Shape& sh) {
   L.cx = take((size_t)(sh.Nx + 1) * (sh.Nx + 1) * dsz);
   L.phiy = take((size_t)sh.Qy * (sh.Ny + 1) * dsz);
   L.phiz = take((size_t)sh.Qz * (sh.Nz + 1) * dsz);
+  L.ptab = take((size_t)sh.V * 16 * dsz);
   L.inst = take((size_t)sh.B * sizeof(InstDev));
   L.inv_dx = take((size_t)sh.B * sh.S * dsz);
   L.g_rest = take((size_t)sh.B * sh.V * dsz);
@@ -119,26 +120,26 @@ static double node_x(double s, int S, double A) {
 }
 
 static int default_cells(const Shape& sh) {
-  // enough node chunks to fill the device for one instance, long marches for batches
+  // long marches amortise the halo re-reads and per-block setup; short ones fill the
+  // device when there are few instances
   const long long pairs = (long long)sh.B * sh.S * sh.V;
-  if (pairs >= (1LL << 24)) return 16;
-  if (pairs >= (1LL << 21)) return 8;
+  if (pairs >= (1LL << 24)) return 32;
+  if (pairs >= (1LL << 21)) return 16;
   return 4;
 }
 
 static int default_waves(const Shape& sh) {
   const int wv = (sh.V + 63) / 64;
-  // smallest waves-per-block in 4..16 that wastes the fewest lanes
-  int best = 4, best_waste = 1 << 30;
-  for (int w = 4; w <= 16; ++w) {
-    const int nvb = (wv + w - 1) / w;
-    const int waste = nvb * w - wv;
-    if (waste < best_waste) {
+  // waves per block in 1..MAX_WAVES with the fewest idle lanes, larger on ties
+  int best = 1, best_waste = 1 << 30;
+  for (int w = 1; w <= MAX_WAVES; ++w) {
+    const int waste = ((wv + w - 1) / w) * w - wv;
+    if (waste <= best_waste) {
       best = w;
       best_waste = waste;
     }
   }
-  return std::min(best, std::max(1, wv));
+  return best;
 }
 
 extern "C" {
@@ -246,6 +247,7 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
   d.cx = (const double*)(w + L.cx);
   d.phiy = (const double*)(w + L.phiy);
   d.phiz = (const double*)(w + L.phiz);
+  d.ptab = (double*)(w + L.ptab);
   d.inst = (InstDev*)(w + L.inst);
   d.inv_dx = (double*)(w + L.inv_dx);
   d.g_rest = (double*)(w + L.g_rest);
@@ -423,9 +425,9 @@ int hrlb_set_state(hrlb_sim* s, const double* d_in) {
 int hrlb_set_launch(hrlb_sim* s, int cells, int waves) {
   if (!s) return fail(HRLB_EINVAL, "set_launch: sim is NULL");
   if (cells == 0) cells = default_cells(s->sh);
-  if (cells != 1 && cells != 2 && cells != 4 && cells != 8 && cells != 16 && cells != 32)
-    return fail(HRLB_EINVAL, "set_launch: cells must be 1, 2, 4, 8, 16 or 32");
-  if (waves < 1 || waves > 16) return fail(HRLB_EINVAL, "set_launch: waves must be in 1..16");
+  if (waves == 0) waves = default_waves(s->sh);
+  if (cells < 1 || cells > 4096) return fail(HRLB_EINVAL, "set_launch: cells must be in 1..4096");
+  if (waves < 1 || waves > MAX_WAVES) return fail(HRLB_EINVAL, "set_launch: waves must be in 1..4");
   // the partials in flight keep their own block count (part_nvb)
   s->cells = cells;
   s->waves = waves;

@@ -15,6 +15,7 @@ constexpr int QX_MAX = 128;
 constexpr int REC_HEAD = 16;  // scalars at the head of a per-node closure record
 constexpr int PART_STRIDE = 16;  // doubles per (block, node) moment partial (13 used)
 constexpr int NMOM = 13;
+constexpr int MAX_WAVES = 4;   // waves per stage-kernel workgroup (LDS: ~10.4 KB per wave)
 
 // Host quadrature tables (double, rounded from long double).
 struct QuadTables {
@@ -51,6 +52,7 @@ struct DevPtrs {
   const double* cx;   // [Nx+1][Nx+1]
   const double* phiy; // [Qy][Ny+1]
   const double* phiz; // [Qz][Nz+1]
+  double* ptab;       // [V][16]: moment multipliers of each velocity (filled on the device)
   // per instance
   InstDev* inst;      // [B]
   double* inv_dx;     // [B][S]
@@ -76,7 +78,7 @@ struct Shape {
 
 // Work-buffer carve-up; returns the total bytes and fills offsets.
 struct WorkLayout {
-  size_t px, py, pz, phix, cx, phiy, phiz, inst, inv_dx, g_rest, g_wall, partials, rec, nw, resid_part,
+  size_t px, py, pz, phix, cx, phiy, phiz, ptab, inst, inv_dx, g_rest, g_wall, partials, rec, nw, resid_part,
       resid, flags, total;
   int nvb_max, nres_max;
 };

@@ -162,6 +162,16 @@ __global__ void __launch_bounds__(256) setup_tables_kernel(Shape sh, DevPtrs d) 
     gyw[j] = full_node(d.phiy, sh.Ny, j, aw);
   }
   for (int k = threadIdx.x; k < sh.Qz; k += blockDim.x) gz0[k] = full_node(d.phiz, sh.Nz, k, a0);
+  if (b == 0) {
+    // moment multipliers of each velocity, the A operand of the moment contraction
+    for (int v = threadIdx.x; v < sh.V; v += blockDim.x) {
+      const int i = v / sh.QyQz, jk = v - i * sh.QyQz, j = jk / sh.Qz, k = jk - j * sh.Qz;
+      const double px = d.px[i], py = d.py[j], pz = d.pz[k], p2 = px * px + py * py + pz * pz;
+      const double m[16] = {1.0, px, py, pz, px * px, py * py, pz * pz, px * py, px * pz, py * pz,
+                            p2 * px, p2 * py, p2 * pz, 0.0, 0.0, 0.0};
+      for (int q = 0; q < 16; ++q) d.ptab[(size_t)v * 16 + q] = m[q];
+    }
+  }
   __syncthreads();
   double acc = 0.0;
   for (int v = threadIdx.x; v < sh.V; v += blockDim.x) {
@@ -194,79 +204,86 @@ __global__ void init_state_kernel(Shape sh, DevPtrs d, const double* __restrict_
 }
 
 // ---------------------------------------------------------------------------------------
-// moment partials: per (block, node) the 13 sums over the block's velocities of
-// F {1, p_x, p_y, p_z, p_x^2, p_y^2, p_z^2, p_x p_y, p_x p_z, p_y p_z, |p|^2 p_x, |p|^2 p_y, |p|^2 p_z}
+// moment partials on the matrix cores
+//
+// The 13 moment sums of a node over a wave's 64 velocities are a dense contraction over
+// the velocity axis: D[m][n] = sum_v P[v][m] F[n][v] for 16 nodes n at a time, with
+// P[v][.] = {1, p_x, p_y, p_z, p_x^2, p_y^2, p_z^2, p_x p_y, p_x p_z, p_y p_z,
+// |p|^2 p_x, |p|^2 p_y, |p|^2 p_z, 0, 0, 0}.  Each wave parks the 16 node rows of F it has
+// produced in LDS and issues 16 v_mfma_f64_16x16x4 (K = 4 velocities each); the
+// operand layouts are A[m][k] in lane m + 16k, B[k][n] in lane n + 16k, and
+// D[4(l/16) + r][l % 16] in lane l, register r.
 
-struct VelMul {
-  double m[NMOM];
-};
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ VelMul velocity_multipliers(double px, double py, double pz, bool active) {
-  VelMul r;
-  const double p2 = px * px + py * py + pz * pz;
-  r.m[0] = active ? 1.0 : 0.0;
-  r.m[1] = active ? px : 0.0;
-  r.m[2] = active ? py : 0.0;
-  r.m[3] = active ? pz : 0.0;
-  r.m[4] = active ? px * px : 0.0;
-  r.m[5] = active ? py * py : 0.0;
-  r.m[6] = active ? pz * pz : 0.0;
-  r.m[7] = active ? px * py : 0.0;
-  r.m[8] = active ? px * pz : 0.0;
-  r.m[9] = active ? py * pz : 0.0;
-  r.m[10] = active ? p2 * px : 0.0;
-  r.m[11] = active ? p2 * py : 0.0;
-  r.m[12] = active ? p2 * pz : 0.0;
-  return r;
-}
+constexpr int FT_LD = 65;                 // padded LDS row (doubles) of a wave's node tile
+constexpr int FT_WAVE = 16 * FT_LD;       // doubles per wave tile
+constexpr int RED_WAVE = 16 * 16;         // doubles per wave of reduced moments (node x moment)
 
-// wave-reduce the 13 weighted sums of f for node slot u and stash them in LDS
-__device__ __forceinline__ void stash_moments(double f, const VelMul& vm, double* red, int wave, int u, int cs,
-                                              int lane) {
+// load this lane's A operands: a[t] = P[v0 + 4t + lane/16][lane % 16] (0 beyond V)
+__device__ __forceinline__ void load_moment_operands(const double* __restrict__ ptab, int wave_v0, int V, int lane,
+                                                     double* a) {
 #pragma unroll
-  for (int q = 0; q < NMOM; ++q) {
-    const double s = wave_sum(f * vm.m[q]);
-    if (lane == 0) red[(wave * cs + u) * NMOM + q] = s;
+  for (int t = 0; t < 16; ++t) {
+    const int v = wave_v0 + 4 * t + (lane >> 4);
+    a[t] = (v < V) ? ptab[(size_t)v * 16 + (lane & 15)] : 0.0;
   }
 }
 
-// sum the per-wave stashes over the block's waves and write the block's partials
-__device__ __forceinline__ void flush_moments(const double* red, int waves, int cs, int nloc, double* __restrict__ out) {
-  for (int idx = threadIdx.x; idx < nloc * NMOM; idx += blockDim.x) {
-    const int u = idx / NMOM, q = idx - u * NMOM;
+__device__ __forceinline__ dbl4 moment_mfma(const double* ft, const double* a, int lane) {
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int n = lane & 15, kk = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], ft[n * FT_LD + 4 * t + kk], acc, 0, 0, 0);
+  return acc;
+}
+
+// after every wave has stored its group of up to 16 node rows in its tile: contract, sum
+// over the block's waves and write the block's partials for nodes s .. s+cnt-1.
+__device__ __forceinline__ void flush_group(double* lds_ft, double* lds_red, const double* a, int wave, int waves,
+                                            int lane, int cnt, double* __restrict__ out) {
+  __syncthreads();
+  const dbl4 acc = moment_mfma(lds_ft + wave * FT_WAVE, a, lane);
+  double* r = lds_red + wave * RED_WAVE + (lane & 15) * 16 + 4 * (lane >> 4);
+  r[0] = acc[0];
+  r[1] = acc[1];
+  r[2] = acc[2];
+  r[3] = acc[3];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < cnt * NMOM; idx += blockDim.x) {
+    const int n = idx / NMOM, q = idx - n * NMOM;
     double s = 0.0;
-    for (int w = 0; w < waves; ++w) s += red[(w * cs + u) * NMOM + q];
-    out[(size_t)u * PART_STRIDE + q] = s;
+    for (int w = 0; w < waves; ++w) s += lds_red[w * RED_WAVE + n * 16 + q];
+    out[(size_t)n * PART_STRIDE + q] = s;
   }
 }
 
-template <int CS>
-__global__ void __launch_bounds__(1024) partials_kernel(Shape sh, DevPtrs d, const double* __restrict__ F, int nvb,
-                                                        int nch) {
-  extern __shared__ double red[];
+__global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, const double* __restrict__ F, int nvb,
+                                                       int nch, int cs) {
+  extern __shared__ double lds[];
+  const int waves = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* lds_ft = lds;
+  double* lds_red = lds + waves * FT_WAVE;
   int t = xcd_tile(blockIdx.x, gridDim.x);
   const int ch = t % nch;
   t /= nch;
   const int vb = t % nvb, b = t / nvb;
   const int S = sh.S, V = sh.V;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, waves = blockDim.x >> 6;
   const int v = vb * blockDim.x + threadIdx.x;
   const bool active = v < V;
-  const int vv = active ? v : V - 1;
-  const int i = vv / sh.QyQz, jk = vv - i * sh.QyQz, j = jk / sh.Qz, k = jk - j * sh.Qz;
-  const VelMul vm = velocity_multipliers(d.px[i], d.py[j], d.pz[k], active);
-  const int s0 = ch * CS;
-  const int nloc = min(CS, S - s0);
+  double a[16];
+  load_moment_operands(d.ptab, vb * blockDim.x + wave * 64, V, lane, a);
+  const int s0 = ch * cs;
+  const int nloc = min(cs, S - s0);
   const double* Fb = F + (size_t)b * S * V;
-#pragma unroll
-  for (int u = 0; u < CS; ++u) {
-    if (u < nloc) {
-      const double f = active ? Fb[(size_t)(s0 + u) * V + v] : 0.0;
-      stash_moments(f, vm, red, wave, u, CS, lane);
-    }
+  double* ft = lds_ft + wave * FT_WAVE;
+  double* part = d.partials + (((size_t)b * nvb + vb) * S + s0) * PART_STRIDE;
+  for (int g = 0; g < nloc; g += 16) {
+    const int cnt = min(16, nloc - g);
+    for (int u = 0; u < 16; ++u) ft[u * FT_LD + lane] = (u < cnt && active) ? Fb[(size_t)(s0 + g + u) * V + v] : 0.0;
+    flush_group(lds_ft, lds_red, a, wave, waves, lane, cnt, part + (size_t)g * PART_STRIDE);
+    __syncthreads();
   }
-  __syncthreads();
-  flush_moments(red, waves, CS, nloc, d.partials + (((size_t)b * nvb + vb) * S + s0) * PART_STRIDE);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -381,123 +398,151 @@ __global__ void __launch_bounds__(64) closure_kernel(Shape sh, DevPtrs d, const 
 // ---------------------------------------------------------------------------------------
 // the stage kernel
 
-template <int SCHEME, int STAGE, int CS>
-__global__ void __launch_bounds__(1024) stage_kernel(Shape sh, DevPtrs d, const double* __restrict__ Fin,
-                                                     const double* Fl, double* Fout, int nvb, int nch) {
-  extern __shared__ double red[];
+// value of node c for a thread's velocity before ghost completion: interior nodes are
+// loaded, nodes left of the centre line are the bounce-back images of nodes 1..3
+// (Eq. widetildei: F_{1-m; i j k} = F_{m; i~ j~ k}), nodes beyond the wall are 0 here
+__device__ __forceinline__ double raw_node(const double* __restrict__ Fb, int c, int S, int V, int v, int vm,
+                                           bool active) {
+  if (!active) return 0.0;
+  if (c >= 0 && c < S) return Fb[(size_t)c * V + v];
+  if (c < 0) return Fb[(size_t)(-c - 1) * V + vm];
+  return 0.0;
+}
+
+// complete a node beyond the wall (App. A.4): p_x > 0 by quadratic extrapolation from the
+// three nodes below (f1 nearest), p_x < 0 the wall Maxwellian n_w F^eq_w; nodes past
+// the third ghost are never read
+__device__ __forceinline__ double ghost_node(double raw, int c, int S, bool pos, double f1, double f2, double f3,
+                                             const double* ex, double ghost_in) {
+  if (c < S) return raw;
+  if (c == S) return pos ? ex[0] * f1 + ex[1] * f2 + ex[2] * f3 : ghost_in;
+  if (c == S + 1) return pos ? ex[3] * f1 + ex[4] * f2 + ex[5] * f3 : ghost_in;
+  return pos ? 0.0 : ghost_in;
+}
+
+template <int SCHEME>
+__device__ __forceinline__ double stencil_flux(bool pos, double px, double w0, double w1, double w2, double w3,
+                                               double w4, double w5) {
+  // upwind-ordered stencil of the interface between w2 and w3 (nodes c, c+1):
+  // p_x > 0: (c-2 .. c+2); p_x < 0: mirrored (c+3 .. c-1)
+  const double a = pos ? w0 : w5, b = pos ? w1 : w4, c = pos ? w2 : w3, dd = pos ? w3 : w2, e = pos ? w4 : w1;
+  return px * interp<SCHEME>(a, b, c, dd, e);
+}
+
+template <int SCHEME, int STAGE>
+__global__ void __launch_bounds__(256) stage_kernel(Shape sh, DevPtrs d, const double* __restrict__ Fin,
+                                                    const double* Fl, double* Fout, int nvb, int nch, int cs) {
+  extern __shared__ double lds[];
+  const int waves = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* lds_ft = lds;
+  double* lds_red = lds + waves * FT_WAVE;
+  double* lds_res = lds_red + waves * RED_WAVE;
   int t = xcd_tile(blockIdx.x, gridDim.x);
   const int ch = t % nch;
   t /= nch;
   const int vb = t % nvb, b = t / nvb;
   const int S = sh.S, V = sh.V, Qx = sh.Qx;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, waves = blockDim.x >> 6;
   const int v = vb * blockDim.x + threadIdx.x;
   const bool active = v < V;
   const int vv = active ? v : V - 1;
   const int i = vv / sh.QyQz, jk = vv - i * sh.QyQz, j = jk / sh.Qz, k = jk - j * sh.Qz;
   const double px = d.px[i], py = d.py[j], pz = d.pz[k];
   const bool pos = px > 0.0;
-  // bounce-back partner (Eq. widetildei): p_x and p_y reversed, p_z kept
-  const int vm = ((2 * Qx - 1 - i) * sh.Qy + (sh.Qy - 1 - j)) * sh.Qz + k;
+  const int vm = ((2 * Qx - 1 - i) * sh.Qy + (sh.Qy - 1 - j)) * sh.Qz + k;  // bounce-back partner
   const size_t base = (size_t)b * S * V;
   const double* Fb = Fin + base;
-  const InstDev& in = d.inst[b];
-  const double dt = in.dt;
-  const int s0 = ch * CS;
-  const int nloc = min(CS, S - s0);
-
-  // window of nodes s0-3 .. s0+CS+2 (0-based node c), ghosts synthesised in registers
-  double w[CS + 6];
+  const InstDev* in = d.inst + b;
+  const double dt = in->dt;
+  double ex[6];
 #pragma unroll
-  for (int q = 0; q < CS + 6; ++q) {
-    const int c = s0 - 3 + q;
-    double val = 0.0;
-    if (active) {
-      if (c >= 0 && c < S)
-        val = Fb[(size_t)c * V + v];
-      else if (c < 0)
-        val = Fb[(size_t)(-c - 1) * V + vm];  // F_{1-m; i j k} = F_{m; i~ j~ k}
-    }
-    w[q] = val;
-  }
-  if (s0 + CS + 2 >= S) {
-    const double ghost_in = active ? d.nw[b] * d.g_wall[(size_t)b * V + vv] : 0.0;
-#pragma unroll
-    for (int q = 3; q < CS + 6; ++q) {
-      const int c = s0 - 3 + q;
-      if (c == S)
-        w[q] = pos ? in.ex[0] * w[q - 1] + in.ex[1] * w[q - 2] + in.ex[2] * w[q - 3] : ghost_in;
-      else if (c == S + 1)
-        w[q] = pos ? in.ex[3] * w[q - 1] + in.ex[4] * w[q - 2] + in.ex[5] * w[q - 3] : ghost_in;
-      else if (c == S + 2)
-        w[q] = pos ? 0.0 : ghost_in;
-    }
-  }
-
-  const VelMul vmul = velocity_multipliers(px, py, pz, active);
+  for (int q = 0; q < 6; ++q) ex[q] = in->ex[q];
+  const double ghost_in = active ? d.nw[b] * d.g_wall[(size_t)b * V + vv] : 0.0;
+  double a[16];
+  load_moment_operands(d.ptab, vb * blockDim.x + wave * 64, V, lane, a);
+  const int s0 = ch * cs;
+  const int nloc = min(cs, S - s0);
   const double* invdx = d.inv_dx + (size_t)b * S;
+  const double* recb = d.rec + (size_t)b * S * sh.rec_len;
+  double* ft = lds_ft + wave * FT_WAVE;
+  double* part = d.partials + (((size_t)b * nvb + vb) * S + s0) * PART_STRIDE;
+
+  // window W0..W5 = nodes c-2 .. c+3, first for c = s0 - 1
+  double W0 = raw_node(Fb, s0 - 3, S, V, v, vm, active);
+  double W1 = raw_node(Fb, s0 - 2, S, V, v, vm, active);
+  double W2 = raw_node(Fb, s0 - 1, S, V, v, vm, active);
+  double W3 = raw_node(Fb, s0, S, V, v, vm, active);
+  double W4 = raw_node(Fb, s0 + 1, S, V, v, vm, active);
+  double W5 = raw_node(Fb, s0 + 2, S, V, v, vm, active);
+  W3 = ghost_node(W3, s0, S, pos, W2, W1, W0, ex, ghost_in);
+  W4 = ghost_node(W4, s0 + 1, S, pos, W3, W2, W1, ex, ghost_in);
+  W5 = ghost_node(W5, s0 + 2, S, pos, W4, W3, W2, ex, ghost_in);
+  double fl = stencil_flux<SCHEME>(pos, px, W0, W1, W2, W3, W4, W5);
+  double nxt = raw_node(Fb, s0 + 3, S, V, v, vm, active);
   double rd = 0.0, rf = 0.0;
 
-  // interface flux between window slots q and q+1
-  auto flux = [&](int q) -> double {
-    const double r = pos ? interp<SCHEME>(w[q - 2], w[q - 1], w[q], w[q + 1], w[q + 2])
-                         : interp<SCHEME>(w[q + 3], w[q + 2], w[q + 1], w[q], w[q - 1]);
-    return px * r;
-  };
-  double fl = flux(2);
-#pragma unroll
-  for (int u = 0; u < CS; ++u) {
-    if (u < nloc) {
-      const int c = s0 + u;
-      const double fr = flux(u + 3);
-      const double D = (fr - fl) * invdx[c];
-      fl = fr;
-      const double F = w[u + 3];
-      const double* rec = d.rec + ((size_t)b * S + c) * sh.rec_len;
-      const double feq = rec[REC_HEAD + i] * rec[REC_HEAD + 2 * Qx + jk];
-      const double Cs = rec[4];
-      double FS = feq;
-      if (Cs != 0.0) {
-        const double xx = px - rec[0], xy = py - rec[1], xz = pz - rec[2];
-        const double xi2 = xx * xx + xy * xy + xz * xz;
-        const double qxi = rec[6] * xx + rec[7] * xy + rec[8] * xz;
-        FS = feq + feq * ((rec[5] * xi2 - Cs) * qxi);  // F^eq (1 + S), Eq. sdef
-      }
-      const double L = (FS - F) * rec[3] - D;  // Eq. L_def
-      const double G = F + dt * L;
-      double out;
-      if constexpr (STAGE == 1) {
-        out = G;
-      } else {
-        const double fl0 = active ? Fl[base + (size_t)c * V + v] : 0.0;
-        if constexpr (STAGE == 2)
+  for (int g = 0; g < nloc; g += 16) {
+    const int cnt = min(16, nloc - g);
+    for (int u = 0; u < 16; ++u) {
+      double out = 0.0;
+      if (u < cnt) {
+        const int c = s0 + g + u;
+        const double Wn = ghost_node(nxt, c + 3, S, pos, W5, W4, W3, ex, ghost_in);
+        nxt = raw_node(Fb, c + 4, S, V, v, vm, active);  // prefetch the next window node
+        W0 = W1;
+        W1 = W2;
+        W2 = W3;
+        W3 = W4;
+        W4 = W5;
+        W5 = Wn;
+        double fl0 = 0.0;
+        if constexpr (STAGE != 1) fl0 = active ? Fl[base + (size_t)c * V + v] : 0.0;
+        const double fr = stencil_flux<SCHEME>(pos, px, W0, W1, W2, W3, W4, W5);
+        const double D = (fr - fl) * invdx[c];  // Eq. flux
+        fl = fr;
+        const double F = W2;
+        const double* rec = recb + (size_t)c * sh.rec_len;
+        const double feq = rec[REC_HEAD + i] * rec[REC_HEAD + 2 * Qx + jk];
+        const double Cs = rec[4];
+        double FS = feq;
+        if (Cs != 0.0) {
+          const double xx = px - rec[0], xy = py - rec[1], xz = pz - rec[2];
+          const double xi2 = xx * xx + xy * xy + xz * xz;
+          const double qxi = rec[6] * xx + rec[7] * xy + rec[8] * xz;
+          FS = feq + feq * ((rec[5] * xi2 - Cs) * qxi);  // F^eq (1 + S), Eq. sdef
+        }
+        const double G = F + dt * ((FS - F) * rec[3] - D);  // F + dt L[F], Eq. L_def
+        if constexpr (STAGE == 1) {
+          out = G;
+        } else if constexpr (STAGE == 2) {
           out = 0.75 * fl0 + 0.25 * G;
-        else
+        } else {
           out = (1.0 / 3.0) * fl0 + (2.0 / 3.0) * G;
-        if constexpr (STAGE == 3) {
           const double dlt = out - fl0;
           rd += dlt * dlt;
           rf += fl0 * fl0;
         }
+        if (active) {
+          Fout[base + (size_t)c * V + v] = out;
+        } else {
+          out = 0.0;
+        }
       }
-      if (active) Fout[base + (size_t)c * V + v] = out;
-      stash_moments(active ? out : 0.0, vmul, red, wave, u, CS, lane);
+      ft[u * FT_LD + lane] = out;
     }
+    flush_group(lds_ft, lds_red, a, wave, waves, lane, cnt, part + (size_t)g * PART_STRIDE);
+    __syncthreads();
   }
   if constexpr (STAGE == 3) {
     rd = wave_sum(rd);
     rf = wave_sum(rf);
     if (lane == 0) {
-      red[waves * CS * NMOM + 2 * wave] = rd;
-      red[waves * CS * NMOM + 2 * wave + 1] = rf;
+      lds_res[2 * wave] = rd;
+      lds_res[2 * wave + 1] = rf;
     }
-  }
-  __syncthreads();
-  flush_moments(red, waves, CS, nloc, d.partials + (((size_t)b * nvb + vb) * S + s0) * PART_STRIDE);
-  if constexpr (STAGE == 3) {
+    __syncthreads();
     if (threadIdx.x < 2) {
       double s = 0.0;
-      for (int wv = 0; wv < waves; ++wv) s += red[waves * CS * NMOM + 2 * wv + threadIdx.x];
+      for (int wv = 0; wv < waves; ++wv) s += lds_res[2 * wv + threadIdx.x];
       d.resid_part[((size_t)b * nvb * nch + (size_t)vb * nch + ch) * 2 + threadIdx.x] = s;
     }
   }
@@ -545,25 +590,14 @@ int launch_init_state(const Shape& sh, const DevPtrs& d, const double* perturb, 
   return (int)hipGetLastError();
 }
 
-template <int CS>
-static int launch_partials_cs(const Shape& sh, const DevPtrs& d, const double* F, int waves, void* stream) {
-  int nvb, nch;
-  const int nblk = grid_tiles(sh, CS, waves, &nvb, &nch);
-  const size_t lds = (size_t)waves * CS * NMOM * sizeof(double);
-  hipLaunchKernelGGL(partials_kernel<CS>, dim3(nblk), dim3(64 * waves), lds, (hipStream_t)stream, sh, d, F, nvb, nch);
-  return (int)hipGetLastError();
-}
+static size_t stage_lds_bytes(int waves) { return ((size_t)waves * (FT_WAVE + RED_WAVE) + 2 * waves) * sizeof(double); }
 
 int launch_partials(const Shape& sh, const DevPtrs& d, const double* F, int cells, int waves, void* stream) {
-  switch (cells) {
-    case 1: return launch_partials_cs<1>(sh, d, F, waves, stream);
-    case 2: return launch_partials_cs<2>(sh, d, F, waves, stream);
-    case 4: return launch_partials_cs<4>(sh, d, F, waves, stream);
-    case 8: return launch_partials_cs<8>(sh, d, F, waves, stream);
-    case 16: return launch_partials_cs<16>(sh, d, F, waves, stream);
-    case 32: return launch_partials_cs<32>(sh, d, F, waves, stream);
-  }
-  return (int)hipErrorInvalidValue;
+  int nvb, nch;
+  const int nblk = grid_tiles(sh, cells, waves, &nvb, &nch);
+  hipLaunchKernelGGL(partials_kernel, dim3(nblk), dim3(64 * waves), stage_lds_bytes(waves), (hipStream_t)stream, sh, d,
+                     F, nvb, nch, cells);
+  return (int)hipGetLastError();
 }
 
 int launch_closure(const Shape& sh, const DevPtrs& d, const double* Fin, int nvb, double* mom_out, void* stream) {
@@ -572,41 +606,26 @@ int launch_closure(const Shape& sh, const DevPtrs& d, const double* Fin, int nvb
   return (int)hipGetLastError();
 }
 
-template <int SCHEME, int STAGE, int CS>
-static int launch_stage_t(const Shape& sh, const DevPtrs& d, const double* Fin, const double* Fl, double* Fout,
-                          int waves, void* stream) {
-  int nvb, nch;
-  const int nblk = grid_tiles(sh, CS, waves, &nvb, &nch);
-  const size_t lds = ((size_t)waves * CS * NMOM + 2 * waves) * sizeof(double);
-  hipLaunchKernelGGL((stage_kernel<SCHEME, STAGE, CS>), dim3(nblk), dim3(64 * waves), lds, (hipStream_t)stream, sh,
-                     d, Fin, Fl, Fout, nvb, nch);
-  return (int)hipGetLastError();
-}
-
 template <int SCHEME, int STAGE>
-static int launch_stage_s(const Shape& sh, const DevPtrs& d, const double* Fin, const double* Fl, double* Fout,
+static int launch_stage_t(const Shape& sh, const DevPtrs& d, const double* Fin, const double* Fl, double* Fout,
                           int cells, int waves, void* stream) {
-  switch (cells) {
-    case 1: return launch_stage_t<SCHEME, STAGE, 1>(sh, d, Fin, Fl, Fout, waves, stream);
-    case 2: return launch_stage_t<SCHEME, STAGE, 2>(sh, d, Fin, Fl, Fout, waves, stream);
-    case 4: return launch_stage_t<SCHEME, STAGE, 4>(sh, d, Fin, Fl, Fout, waves, stream);
-    case 8: return launch_stage_t<SCHEME, STAGE, 8>(sh, d, Fin, Fl, Fout, waves, stream);
-    case 16: return launch_stage_t<SCHEME, STAGE, 16>(sh, d, Fin, Fl, Fout, waves, stream);
-    case 32: return launch_stage_t<SCHEME, STAGE, 32>(sh, d, Fin, Fl, Fout, waves, stream);
-  }
-  return (int)hipErrorInvalidValue;
+  int nvb, nch;
+  const int nblk = grid_tiles(sh, cells, waves, &nvb, &nch);
+  hipLaunchKernelGGL((stage_kernel<SCHEME, STAGE>), dim3(nblk), dim3(64 * waves), stage_lds_bytes(waves),
+                     (hipStream_t)stream, sh, d, Fin, Fl, Fout, nvb, nch, cells);
+  return (int)hipGetLastError();
 }
 
 int launch_stage(const Shape& sh, const DevPtrs& d, int stage, const double* Fin, const double* Fl, double* Fout,
                  int cells, int waves, void* stream) {
   if (sh.scheme == 1) {
-    if (stage == 1) return launch_stage_s<1, 1>(sh, d, Fin, Fl, Fout, cells, waves, stream);
-    if (stage == 2) return launch_stage_s<1, 2>(sh, d, Fin, Fl, Fout, cells, waves, stream);
-    return launch_stage_s<1, 3>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+    if (stage == 1) return launch_stage_t<1, 1>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+    if (stage == 2) return launch_stage_t<1, 2>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+    return launch_stage_t<1, 3>(sh, d, Fin, Fl, Fout, cells, waves, stream);
   }
-  if (stage == 1) return launch_stage_s<0, 1>(sh, d, Fin, Fl, Fout, cells, waves, stream);
-  if (stage == 2) return launch_stage_s<0, 2>(sh, d, Fin, Fl, Fout, cells, waves, stream);
-  return launch_stage_s<0, 3>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+  if (stage == 1) return launch_stage_t<0, 1>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+  if (stage == 2) return launch_stage_t<0, 2>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+  return launch_stage_t<0, 3>(sh, d, Fin, Fl, Fout, cells, waves, stream);
 }
 
 int launch_residual(const Shape& sh, const DevPtrs& d, int nres, void* stream) {

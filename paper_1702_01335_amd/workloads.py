@@ -1,9 +1,8 @@
 """Named synthetic workloads (parameter sets only; no solver arithmetic).
 
 Each workload is a dict of the parameters of one Couette instance plus the shared shape
-(velocity set, node count, scheme).  The readings behind each choice (expansion orders,
-time steps, laws where the workload's description is silent) are documented with the
-design notes of the repository.
+(velocity set, node count, scheme).  Expansion orders follow the paper's choice
+N_x = min(6, Qx - 1) and N = Q - 1 on y and z; time steps keep the Courant number near 0.4.
 
   couette_bgk_s64_v128     BGK (Pr = 1, mu ~ T), Kn = 0.1, u_w = 0.1, 64 equidistant nodes,
                            HHLB(3;4) x HLB(3;4) x HLB(3;4) (V = 128), 2nd-order upwind,

@@ -1,7 +1,7 @@
 """Helpers of the GPU parity tests: run the same seeded instance through the HIP library and
 through the oracle, and compare the populations.
 
-Tolerance (derived; see the design notes): with rounding only, the two FP64 paths agree to
+Tolerance (derived): with rounding only, the two FP64 paths agree to
 a few ulp per operation, accumulated over the stages.  Two scales are checked:
   * normwise: max |F_gpu - F_oracle| / max |F_oracle| <= 1e-12;
   * per velocity column: max_s |F_gpu - F_oracle| / max_s |F_oracle| <= max(1e-10, 1e-15 kappa_v),
