@@ -36,6 +36,7 @@ def parse():
     ap.add_argument('--cells', type=int, default=0)
     ap.add_argument('--waves', type=int, default=0)
     ap.add_argument('--no-cpu', action='store_true')
+    ap.add_argument('--eager', action='store_true', help='launch kernels one by one instead of replaying a HIP graph')
     ap.add_argument('--cpu-seconds', type=float, default=15.0)
     return ap.parse_args()
 
@@ -108,6 +109,7 @@ def main():
         c0, w0 = solver.get_launch()
         solver.set_launch(args.cells or c0, args.waves or w0)
     cells, waves = solver.get_launch()
+    solver.set_graph(not args.eager)
     pairs = args.batch * wl['S'] * q.V
     ms, wall = time_steps(solver, args.steps, args.warmup)
     value = pairs / (ms * 1e-3) / 1e9
@@ -125,6 +127,7 @@ def main():
 
     # single instance of the same workload (latency-bound; reported for context)
     q1, s1 = make_solver(wl, 1, device)
+    s1.set_graph(not args.eager)
     ms1, _ = time_steps(s1, max(args.steps, 50), args.warmup)
     single = dict(batch=1, ms_per_step=ms1, value=wl['S'] * q1.V / (ms1 * 1e-3) / 1e9)
     del s1
@@ -144,7 +147,8 @@ def main():
         'data': 'synthetic',
         'config': {'workload': f"{args.workload} x {args.batch} independent seeded instances",
                    'batch': args.batch, 'S': wl['S'], 'V': q.V, 'Qx': wl['Qx'], 'Qy': wl['Qy'], 'Qz': wl['Qz'],
-                   'scheme': wl['scheme'], 'pairs': pairs, 'launch': {'cells': cells, 'waves': waves},
+                   'scheme': wl['scheme'], 'pairs': pairs,
+                   'launch': {'cells': cells, 'waves': waves, 'graph': not args.eager},
                    'parallelism': 'single GPU'},
         'hbm_frac_step': pairs * BYTES_PER_PAIR_STEP / (ms * 1e-3) / HBM_PEAK,
         'roofline': {'bound': 'hbm', 'achieved': achieved / 1e9, 'peak': HBM_PEAK / 1e9, 'unit': 'GB/s',

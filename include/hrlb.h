@@ -156,6 +156,26 @@ int hrlb_set_launch(hrlb_sim* sim, int cells, int waves);
 int hrlb_get_launch(const hrlb_sim* sim, int* cells, int* waves);
 
 /*
+ * autotune -- choose the stage kernel's launch shape for this sim's (velocity set, S,
+ * batch, scheme) by timing candidate shapes (cells in 2..128, waves in 1..4) with HIP
+ * events over `probe_steps` graph-replayed steps each, and select the fastest.  The probe
+ * steps are real steps: they advance the state.  If `cache_path` names a file holding an
+ * entry for this shape (JSON lines written by an earlier call), that entry is used and
+ * nothing is timed (*best_ms = -1); otherwise the result is appended to the file.
+ * Synchronises the stream.  Errors: HRLB_EINVAL, HRLB_EHIP.
+ */
+int hrlb_autotune(hrlb_sim* sim, int probe_steps, const char* cache_path, int* best_cells, int* best_waves,
+                  double* best_ms);
+
+/*
+ * Graph mode: when on, hrlb_step replays a HIP graph holding one RK3 step (its six
+ * launches, captured on a private stream on first use and after a launch-shape change)
+ * on the sim's stream instead of launching the kernels one by one.  Results are
+ * identical to the eager path.  Timing mode uses the eager path.
+ */
+int hrlb_set_graph(hrlb_sim* sim, int on);
+
+/*
  * Optional per-kernel timing: when on, hrlb_step brackets every launch with HIP events on
  * the sim's stream; hrlb_get_timing synchronises and returns the accumulated device time
  * in ms and launch counts of [0] the stage kernel, [1] the closure kernel.  Turning it on

@@ -7,7 +7,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -51,6 +54,10 @@ struct hrlb_sim {
   int part_nvb;      // nvb of the launch that produced the current moment partials
   int resid_nres;    // residual partial count of the last stage-3 launch (0: none yet)
   bool timing;
+  bool graph_on;
+  hipGraphExec_t gexec;   // one captured RK3 step (valid when gexec != nullptr)
+  hipStream_t cap_stream; // private stream the step is captured on
+  int g_cells, g_waves;   // launch shape the graph was captured with
   std::vector<hipEvent_t> ev;  // pairs (start, stop), kind in ev_kind
   std::vector<int> ev_kind;
   double ms[2];
@@ -236,6 +243,10 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
   s->part_nvb = 0;
   s->resid_nres = 0;
   s->timing = false;
+  s->graph_on = false;
+  s->gexec = nullptr;
+  s->cap_stream = nullptr;
+  s->g_cells = s->g_waves = 0;
   s->ms[0] = s->ms[1] = 0;
   s->launches[0] = s->launches[1] = 0;
   char* w = (char*)d_work;
@@ -327,6 +338,8 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
 void hrlb_sim_free(hrlb_sim* s) {
   if (!s) return;
   for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
 }
 
@@ -350,6 +363,45 @@ static hipError_t ev_end(hrlb_sim* s, hipEvent_t e0, int kind) {
   return e;
 }
 
+// enqueue the six launches of one RK3 step on `st` (no timing events)
+static hipError_t enqueue_step(hrlb_sim* s, hipStream_t st, int part_nvb) {
+  const Shape& sh = s->sh;
+  DevPtrs& d = s->d;
+  const int nvb = (sh.V + 64 * s->waves - 1) / (64 * s->waves);
+  hipError_t e = hipSuccess;
+  for (int stage = 1; stage <= 3 && e == hipSuccess; ++stage) {
+    const double* Fin = d.F[stage - 1];
+    double* Fout = d.F[stage % 3];  // stage 1 -> F[1], 2 -> F[2], 3 -> F[0] (in place over F_l)
+    e = (hipError_t)launch_closure(sh, d, Fin, stage == 1 ? part_nvb : nvb, nullptr, st);
+    if (e == hipSuccess) e = (hipError_t)launch_stage(sh, d, stage, Fin, d.F[0], Fout, s->cells, s->waves, st);
+  }
+  return e;
+}
+
+static hipError_t capture_step(hrlb_sim* s) {
+  hipError_t e = hipSuccess;
+  if (s->gexec) {
+    (void)hipGraphExecDestroy(s->gexec);
+    s->gexec = nullptr;
+  }
+  if (!s->cap_stream) e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  const int nvb = (s->sh.V + 64 * s->waves - 1) / (64 * s->waves);
+  hipGraph_t g = nullptr;
+  e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t el = enqueue_step(s, s->cap_stream, nvb);
+  e = hipStreamEndCapture(s->cap_stream, &g);
+  if (el != hipSuccess) e = el;
+  if (e == hipSuccess) e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e == hipSuccess) {
+    s->g_cells = s->cells;
+    s->g_waves = s->waves;
+  }
+  return e;
+}
+
 int hrlb_step(hrlb_sim* s, int nsteps) {
   if (!s) return fail(HRLB_EINVAL, "step: sim is NULL");
   if (nsteps < 0) return fail(HRLB_EINVAL, "step: nsteps must be >= 0");
@@ -357,7 +409,29 @@ int hrlb_step(hrlb_sim* s, int nsteps) {
   DevPtrs& d = s->d;
   const int nvb = (sh.V + 64 * s->waves - 1) / (64 * s->waves);
   const int nch = (sh.S + s->cells - 1) / s->cells;
-  for (int n = 0; n < nsteps; ++n) {
+  int n = 0;
+  if (s->graph_on && !s->timing) {
+    // the captured step expects partials laid out by its own launch shape; one eager step
+    // re-lays them out after an init, set_state, moments or shape change
+    if (s->part_nvb != nvb && nsteps > 0) {
+      hipError_t e = enqueue_step(s, s->stream, s->part_nvb);
+      if (e != hipSuccess) return hip_fail(e, "step: launch");
+      s->part_nvb = nvb;
+      s->resid_nres = nvb * nch;
+      n = 1;
+    }
+    if (n < nsteps && (!s->gexec || s->g_cells != s->cells || s->g_waves != s->waves)) {
+      hipError_t e = capture_step(s);
+      if (e != hipSuccess) return hip_fail(e, "step: graph capture");
+    }
+    for (; n < nsteps; ++n) {
+      hipError_t e = hipGraphLaunch(s->gexec, s->stream);
+      if (e != hipSuccess) return hip_fail(e, "step: graph launch");
+      s->resid_nres = nvb * nch;
+    }
+    return HRLB_OK;
+  }
+  for (; n < nsteps; ++n) {
     for (int stage = 1; stage <= 3; ++stage) {
       const double* Fin = d.F[stage - 1];
       double* Fout = d.F[stage % 3];  // stage 1 -> F[1], 2 -> F[2], 3 -> F[0] (in place over F_l)
@@ -374,6 +448,107 @@ int hrlb_step(hrlb_sim* s, int nsteps) {
     }
     s->resid_nres = nvb * nch;
   }
+  return HRLB_OK;
+}
+
+static std::string tune_key(const Shape& sh) {
+  std::ostringstream k;
+  k << "Qx" << sh.Qx << "_Qy" << sh.Qy << "_Qz" << sh.Qz << "_S" << sh.S << "_B" << sh.B << "_scheme" << sh.scheme;
+  return k.str();
+}
+
+// cache file: one JSON object per line, {"key": "...", "cells": c, "waves": w, "ms": t}
+static bool tune_lookup(const char* path, const std::string& key, int* cells, int* waves) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    const std::string tag = "\"key\": \"" + key + "\"";
+    if (line.find(tag) == std::string::npos) continue;
+    int c = 0, w = 0;
+    const size_t pc = line.find("\"cells\":"), pw = line.find("\"waves\":");
+    if (pc == std::string::npos || pw == std::string::npos) continue;
+    if (std::sscanf(line.c_str() + pc + 8, "%d", &c) == 1 && std::sscanf(line.c_str() + pw + 8, "%d", &w) == 1 &&
+        c >= 1 && w >= 1 && w <= MAX_WAVES) {
+      *cells = c;
+      *waves = w;
+      found = true;  // the last entry for a key wins
+    }
+  }
+  return found;
+}
+
+int hrlb_autotune(hrlb_sim* s, int probe_steps, const char* cache_path, int* best_cells, int* best_waves,
+                  double* best_ms) {
+  if (!s || !best_cells || !best_waves || !best_ms) return fail(HRLB_EINVAL, "autotune: NULL argument");
+  if (probe_steps < 1) return fail(HRLB_EINVAL, "autotune: probe_steps must be >= 1");
+  const std::string key = tune_key(s->sh);
+  int c = 0, w = 0;
+  if (tune_lookup(cache_path, key, &c, &w)) {
+    s->cells = c;
+    s->waves = w;
+    *best_cells = c;
+    *best_waves = w;
+    *best_ms = -1.0;
+    return HRLB_OK;
+  }
+  const bool graph = s->graph_on, timing = s->timing;
+  s->timing = false;
+  s->graph_on = true;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0), "autotune: event");
+  HIP_TRY(hipEventCreate(&e1), "autotune: event");
+  const int cells_c[] = {2, 4, 8, 16, 32, 64, 128};
+  double best = 1e300;
+  int bc = s->cells, bw = s->waves;
+  int rc = HRLB_OK;
+  for (int wv = 1; wv <= MAX_WAVES && rc == HRLB_OK; ++wv) {
+    for (int ci : cells_c) {
+      if (ci > 2 * s->sh.S) continue;
+      s->cells = ci;
+      s->waves = wv;
+      rc = hrlb_step(s, 2);  // re-lays out the partials and captures the graph of this shape
+      if (rc != HRLB_OK) break;
+      hipError_t e = hipEventRecord(e0, s->stream);
+      if (e == hipSuccess) rc = hrlb_step(s, probe_steps);
+      if (rc != HRLB_OK) break;
+      if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        rc = hip_fail(e, "autotune: timing");
+        break;
+      }
+      const double per = ms / probe_steps;
+      if (per < best) {
+        best = per;
+        bc = ci;
+        bw = wv;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s->cells = bc;
+  s->waves = bw;
+  s->graph_on = graph;
+  s->timing = timing;
+  if (rc != HRLB_OK) return rc;
+  *best_cells = bc;
+  *best_waves = bw;
+  *best_ms = best;
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    f << "{\"key\": \"" << key << "\", \"cells\": " << bc << ", \"waves\": " << bw << ", \"ms\": " << best << "}\n";
+  }
+  return HRLB_OK;
+}
+
+int hrlb_set_graph(hrlb_sim* s, int on) {
+  if (!s) return fail(HRLB_EINVAL, "set_graph: sim is NULL");
+  s->graph_on = on != 0;
   return HRLB_OK;
 }
 

@@ -22,8 +22,8 @@ MOMENT_NAMES = ('n', 'ux', 'uy', 'uz', 'T', 'Pxx', 'Pyy', 'Pzz', 'Pxy', 'Pxz', '
 
 EXPORTS = ('hrlb_last_error', 'hrlb_init_quadrature', 'hrlb_quad_free', 'hrlb_quad_size', 'hrlb_quad_nodes',
            'hrlb_state_bytes', 'hrlb_init_state', 'hrlb_sim_free', 'hrlb_step', 'hrlb_moments', 'hrlb_residual',
-           'hrlb_get_state', 'hrlb_set_state', 'hrlb_set_launch', 'hrlb_get_launch', 'hrlb_set_timing',
-           'hrlb_get_timing')
+           'hrlb_get_state', 'hrlb_set_state', 'hrlb_set_launch', 'hrlb_get_launch', 'hrlb_autotune', 'hrlb_set_graph',
+           'hrlb_set_timing', 'hrlb_get_timing')
 
 
 class HrlbError(RuntimeError):
@@ -77,6 +77,8 @@ def load():
     lib.hrlb_set_state.argtypes = [vp, vp]
     lib.hrlb_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.hrlb_get_launch.argtypes = [vp, ip, ip]
+    lib.hrlb_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ip, ip, dp]
+    lib.hrlb_set_graph.argtypes = [vp, ctypes.c_int]
     lib.hrlb_set_timing.argtypes = [vp, ctypes.c_int]
     lib.hrlb_get_timing.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
     for name in EXPORTS:
@@ -214,6 +216,15 @@ class Solver:
         c, w = ctypes.c_int(), ctypes.c_int()
         _check(load().hrlb_get_launch(self.handle, ctypes.byref(c), ctypes.byref(w)))
         return c.value, w.value
+
+    def autotune(self, probe_steps=5, cache_path=None):
+        c, w, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        path = cache_path.encode() if cache_path else None
+        _check(load().hrlb_autotune(self.handle, probe_steps, path, ctypes.byref(c), ctypes.byref(w), ctypes.byref(ms)))
+        return c.value, w.value, ms.value
+
+    def set_graph(self, on):
+        _check(load().hrlb_set_graph(self.handle, int(bool(on))))
 
     def set_timing(self, on):
         _check(load().hrlb_set_timing(self.handle, int(bool(on))))

@@ -122,3 +122,42 @@ def test_numeric_fault_is_reported():
     solver.step(1)
     rc, _ = solver.residual(raise_on_fault=False)
     assert rc == -4
+
+
+def test_graph_replay_equals_eager_bitwise():
+    """The captured RK3 step replays the same launches: results must be bitwise equal to the
+    eager path, over several replays with eager work and synchronisations in between."""
+    wl = make_wl(5, 3, 3, 13, 'weno5', A=0.9, dt=1e-4)
+    _, _, _, eager = gpu_run(wl, 0, seeds=[31])
+    eager.step(10)
+    Fe = eager.get_state().cpu().numpy()
+    _, _, _, g = gpu_run(wl, 0, seeds=[31])
+    g.set_graph(True)
+    g.step(3)
+    g.synchronize()
+    g.set_graph(False)
+    g.step(2)
+    g.residual()
+    g.set_graph(True)
+    g.step(4)
+    g.synchronize()
+    g.step(1)
+    Fg = g.get_state().cpu().numpy()
+    assert np.array_equal(Fe, Fg)
+
+
+def test_autotune_picks_a_valid_shape_and_caches_it(tmp_path):
+    wl = make_wl(5, 3, 3, 13, 'weno5', A=0.9, dt=1e-4)
+    cache = str(tmp_path / 'tune.jsonl')
+    _, _, _, s = gpu_run(wl, 0, seeds=[41])
+    c, w, ms = s.autotune(probe_steps=2, cache_path=cache)
+    assert c >= 1 and 1 <= w <= 4 and ms > 0
+    assert s.get_launch() == (c, w)
+    # a second sim of the same shape reads the cache without timing
+    _, _, _, s2 = gpu_run(wl, 0, seeds=[42])
+    c2, w2, ms2 = s2.autotune(probe_steps=2, cache_path=cache)
+    assert (c2, w2, ms2) == (c, w, -1.0)
+    # and the tuned shape still matches the oracle
+    Fg, _, _, _ = gpu_run(wl, 3, seeds=[43], launch=(c, w))
+    Fo, m, _ = oracle_run(wl, 3, seed=43)
+    assert_parity(Fg[0], Fo, m, f"tuned cells={c} waves={w}")
