@@ -212,7 +212,7 @@ __global__ void init_state_kernel(Shape sh, DevPtrs d, const double* __restrict_
 // |p|^2 p_x, |p|^2 p_y, |p|^2 p_z, 0, 0, 0}.  Each wave parks the 16 node rows of F it has
 // produced in LDS and issues 16 v_mfma_f64_16x16x4 (K = 4 velocities each); the
 // operand layouts are A[m][k] in lane m + 16k, B[k][n] in lane n + 16k, and
-// D[4(l/16) + r][l % 16] in lane l, register r.
+// D[4r + l/16][l % 16] in lane l, result register r (checked on gfx950).
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -244,11 +244,11 @@ __device__ __forceinline__ void flush_group(double* lds_ft, double* lds_red, con
                                             int lane, int cnt, double* __restrict__ out) {
   __syncthreads();
   const dbl4 acc = moment_mfma(lds_ft + wave * FT_WAVE, a, lane);
-  double* r = lds_red + wave * RED_WAVE + (lane & 15) * 16 + 4 * (lane >> 4);
+  double* r = lds_red + wave * RED_WAVE + (lane & 15) * 16 + (lane >> 4);
   r[0] = acc[0];
-  r[1] = acc[1];
-  r[2] = acc[2];
-  r[3] = acc[3];
+  r[4] = acc[1];
+  r[8] = acc[2];
+  r[12] = acc[3];
   __syncthreads();
   for (int idx = threadIdx.x; idx < cnt * NMOM; idx += blockDim.x) {
     const int n = idx / NMOM, q = idx - n * NMOM;
@@ -517,7 +517,7 @@ __global__ void __launch_bounds__(256) stage_kernel(Shape sh, DevPtrs d, const d
           out = 0.75 * fl0 + 0.25 * G;
         } else {
           out = (1.0 / 3.0) * fl0 + (2.0 / 3.0) * G;
-          const double dlt = out - fl0;
+          const double dlt = active ? out - fl0 : 0.0;
           rd += dlt * dlt;
           rf += fl0 * fl0;
         }
