@@ -37,6 +37,8 @@ def parse():
     ap.add_argument('--waves', type=int, default=0)
     ap.add_argument('--no-cpu', action='store_true')
     ap.add_argument('--eager', action='store_true', help='launch kernels one by one instead of replaying a HIP graph')
+    ap.add_argument('--copy-probe-mib', type=int, default=0,
+                    help='also run one device copy of this size (calibrates HBM byte counters under a profiler)')
     ap.add_argument('--cpu-seconds', type=float, default=15.0)
     return ap.parse_args()
 
@@ -124,6 +126,15 @@ def main():
     bytes_per_launch = pairs * BYTES_PER_PAIR_STEP / 3.0
     achieved = bytes_per_launch / stage_avg_s
     res = solver.residual()
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=device)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # single instance of the same workload (latency-bound; reported for context)
     q1, s1 = make_solver(wl, 1, device)

@@ -95,6 +95,7 @@ WorkLayout work_layout(const Shape& sh) {
   L.resid_part = take((size_t)sh.B * L.nres_max * 2 * dsz);
   L.resid = take((size_t)sh.B * dsz);
   L.flags = take((size_t)sh.B * sizeof(int));
+  L.junk = take(256 * dsz);
   L.total = off;
   return L;
 }
@@ -269,6 +270,7 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
   d.resid_part = (double*)(w + L.resid_part);
   d.resid = (double*)(w + L.resid);
   d.flags = (int*)(w + L.flags);
+  d.junk = (double*)(w + L.junk);
   for (int k = 0; k < 3; ++k) d.F[k] = (double*)((char*)d_state + k * arr);
 
   // host-side per-instance tables

@@ -65,6 +65,7 @@ struct DevPtrs {
   double* resid_part; // [B][nres][2]
   double* resid;      // [B]
   int* flags;         // [B]
+  double* junk;       // [256]: store target of stage-kernel lanes beyond V (never read)
   // populations
   double* F[3];       // three [B][S][V] arrays
 };
@@ -79,7 +80,7 @@ struct Shape {
 // Work-buffer carve-up; returns the total bytes and fills offsets.
 struct WorkLayout {
   size_t px, py, pz, phix, cx, phiy, phiz, ptab, inst, inv_dx, g_rest, g_wall, partials, rec, nw, resid_part,
-      resid, flags, total;
+      resid, flags, junk, total;
   int nvb_max, nres_max;
 };
 WorkLayout work_layout(const Shape& sh);

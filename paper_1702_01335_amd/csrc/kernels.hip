@@ -38,6 +38,14 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
   return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// value of x in lane l (uniform l), as a scalar
+__device__ __forceinline__ double bcast(double x, int l) {
+  const unsigned long long u = __double_as_longlong(x);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, l);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), l);
+  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -238,10 +246,15 @@ __device__ __forceinline__ dbl4 moment_mfma(const double* ft, const double* a, i
   return acc;
 }
 
-// after every wave has stored its group of up to 16 node rows in its tile: contract, sum
-// over the block's waves and write the block's partials for nodes s .. s+cnt-1.
-__device__ __forceinline__ void flush_group(double* lds_ft, double* lds_red, const double* a, int wave, int waves,
-                                            int lane, int cnt, double* __restrict__ out) {
+// after every wave has stored its group of up to 16 node rows in its tile: contract with
+// the multipliers of the wave's velocities (A operands loaded here, from the small,
+// cache-resident multiplier table, so they hold no registers during the march), sum over
+// the block's waves and write the block's partials for nodes s .. s+cnt-1.
+__device__ __forceinline__ void flush_group(double* lds_ft, double* lds_red, const double* __restrict__ ptab,
+                                            int wave_v0, int V, int wave, int waves, int lane, int cnt,
+                                            double* __restrict__ out) {
+  double a[16];
+  load_moment_operands(ptab, wave_v0, V, lane, a);
   __syncthreads();
   const dbl4 acc = moment_mfma(lds_ft + wave * FT_WAVE, a, lane);
   double* r = lds_red + wave * RED_WAVE + (lane & 15) * 16 + (lane >> 4);
@@ -271,8 +284,7 @@ __global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, cons
   const int S = sh.S, V = sh.V;
   const int v = vb * blockDim.x + threadIdx.x;
   const bool active = v < V;
-  double a[16];
-  load_moment_operands(d.ptab, vb * blockDim.x + wave * 64, V, lane, a);
+  const int wave_v0 = vb * blockDim.x + wave * 64;
   const int s0 = ch * cs;
   const int nloc = min(cs, S - s0);
   const double* Fb = F + (size_t)b * S * V;
@@ -281,91 +293,122 @@ __global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, cons
   for (int g = 0; g < nloc; g += 16) {
     const int cnt = min(16, nloc - g);
     for (int u = 0; u < 16; ++u) ft[u * FT_LD + lane] = (u < cnt && active) ? Fb[(size_t)(s0 + g + u) * V + v] : 0.0;
-    flush_group(lds_ft, lds_red, a, wave, waves, lane, cnt, part + (size_t)g * PART_STRIDE);
+    flush_group(lds_ft, lds_red, d.ptab, wave_v0, V, wave, waves, lane, cnt, part + (size_t)g * PART_STRIDE);
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// closure: one 64-lane block per (instance, node), plus one wall block per instance
+// closure: 64 nodes per block (one lane per node for the scalar closure), plus one wall
+// block per instance
+
+constexpr int CL_NODES = 64;             // most nodes per closure block
 
 __global__ void __launch_bounds__(64) closure_kernel(Shape sh, DevPtrs d, const double* __restrict__ Fin, int nvb,
-                                                     double* __restrict__ mom_out) {
+                                                     double* __restrict__ mom_out, int node_blocks, int nb) {
   const int S = sh.S;
-  const int b = blockIdx.x / (S + 1), c = blockIdx.x - b * (S + 1);
   const int lane = threadIdx.x;
-  const InstDev in = d.inst[b];
-  if (c == S) {
+  if ((int)blockIdx.x >= node_blocks) {
     // wall density: zero net mass flux through x = L/2 (App. A.4); the outgoing fluxes
     // (p_x > 0) use the extrapolated ghosts, the incoming ones are p_x n_w F^eq_w exactly.
+    const int b = blockIdx.x - node_blocks;
+    const InstDev* in = d.inst + b;
     const int V = sh.V;
     const double* F = Fin + (size_t)b * S * V;
     double acc = 0.0;
     for (int v = sh.Qx * sh.QyQz + lane; v < V; v += 64) {
       const double px = d.px[v / sh.QyQz];
       const double f3 = F[(size_t)(S - 3) * V + v], f2 = F[(size_t)(S - 2) * V + v], f1 = F[(size_t)(S - 1) * V + v];
-      const double g0 = in.ex[0] * f1 + in.ex[1] * f2 + in.ex[2] * f3;
-      const double g1 = in.ex[3] * g0 + in.ex[4] * f1 + in.ex[5] * f2;
+      const double g0 = in->ex[0] * f1 + in->ex[1] * f2 + in->ex[2] * f3;
+      const double g1 = in->ex[3] * g0 + in->ex[4] * f1 + in->ex[5] * f2;
       const double r = (sh.scheme == 1) ? weno5(f3, f2, f1, g0, g1) : (1.5 * f1 - 0.5 * f2);
       acc += px * r;
     }
     acc = wave_sum(acc);
     if (lane == 0) {
-      const double nw = -acc / in.wall_den;
+      const double nw = -acc / in->wall_den;
       d.nw[b] = nw;
       if (!(nw > 0.0) || !isfinite(nw)) d.flags[b] = 1;
     }
     return;
   }
-  __shared__ double Msh[NMOM];
-  if (lane < NMOM) {
+  // LDS (sizes of this velocity set): moment sums, per-node coefficients, projection
+  // tables, per-node g_y and g_z
+  extern __shared__ double cl_lds[];
+  const int nphx = sh.Qx * (sh.Nx + 1), nphy = sh.Qy * (sh.Ny + 1), nphz = sh.Qz * (sh.Nz + 1);
+  const int oJm = sh.Nx + 1, oay = 2 * (sh.Nx + 1), oaz = oay + sh.Ny + 1, SC = oaz + sh.Nz + 1;
+  const int Qyz = sh.Qy + sh.Qz;
+  double* msum = cl_lds;
+  double* scal = msum + nb * PART_STRIDE;
+  double* phix = scal + nb * SC;
+  double* phiy = phix + nphx;
+  double* phiz = phiy + nphy;
+  double* gyz = phiz + nphz;
+  const int total = sh.B * S;
+  const int g0 = blockIdx.x * nb;
+  const int nblk_nodes = min(nb, total - g0);
+  for (int e = lane; e < nphx; e += 64) phix[e] = d.phix[e];
+  for (int e = lane; e < nphy; e += 64) phiy[e] = d.phiy[e];
+  for (int e = lane; e < nphz; e += 64) phiz[e] = d.phiz[e];
+  // 1) sum the moment partials over velocity blocks: the block's [node][16] tile is read
+  //    with consecutive lanes on consecutive doubles
+  for (int e = lane; e < nblk_nodes * PART_STRIDE; e += 64) {
+    const int nd = e >> 4, q = e & 15;
+    const int g = g0 + nd, b = g / S, c = g - b * S;
+    const double* src = d.partials + ((size_t)b * nvb * S + c) * PART_STRIDE + q;
     double acc = 0.0;
-    for (int vb = 0; vb < nvb; ++vb) acc += d.partials[(((size_t)b * nvb + vb) * S + c) * PART_STRIDE + lane];
-    Msh[lane] = acc;
+    if (q < NMOM)
+      for (int vb = 0; vb < nvb; ++vb) acc += src[(size_t)vb * S * PART_STRIDE];
+    msum[e] = acc;
   }
   __syncthreads();
-  const double n = Msh[0];
-  const double ux = Msh[1] / n, uy = Msh[2] / n, uz = Msh[3] / n;
-  const double Pxx = Msh[4] - n * ux * ux, Pyy = Msh[5] - n * uy * uy, Pzz = Msh[6] - n * uz * uz;
-  const double Pxy = Msh[7] - n * ux * uy, Pxz = Msh[8] - n * ux * uz, Pyz = Msh[9] - n * uy * uz;
-  const double T = (Pxx + Pyy + Pzz) / (3.0 * n);
+  // 2) one lane per node: moments, tau, Shakhov coefficients, projection coefficients
+  const bool live = lane < nblk_nodes;
+  const int g = g0 + (live ? lane : 0), b = g / S, c = g - b * S;
+  (void)c;
+  const InstDev* in = d.inst + b;
+  const double* M = msum + lane * PART_STRIDE;
+  const double n = live ? M[0] : 1.0;
+  const double ux = live ? M[1] / n : 0.0, uy = live ? M[2] / n : 0.0, uz = live ? M[3] / n : 0.0;
+  const double Pxx = M[4] - n * ux * ux, Pyy = M[5] - n * uy * uy, Pzz = M[6] - n * uz * uz;
+  const double Pxy = M[7] - n * ux * uy, Pxz = M[8] - n * ux * uz, Pyz = M[9] - n * uy * uz;
+  const double T = live ? (Pxx + Pyy + Pzz) / (3.0 * n) : 1.0;
   // q_a = 1/2 sum F |p - u|^2 (p_a - u_a), expanded over the raw sums
-  const double M2 = Msh[4] + Msh[5] + Msh[6];
+  const double M2 = M[4] + M[5] + M[6];
   const double u2 = ux * ux + uy * uy + uz * uz;
-  const double qx = 0.5 * (Msh[10] - ux * M2 - 2.0 * (ux * Msh[4] + uy * Msh[7] + uz * Msh[8]) + 2.0 * n * u2 * ux);
-  const double qy = 0.5 * (Msh[11] - uy * M2 - 2.0 * (ux * Msh[7] + uy * Msh[5] + uz * Msh[9]) + 2.0 * n * u2 * uy);
-  const double qz = 0.5 * (Msh[12] - uz * M2 - 2.0 * (ux * Msh[8] + uy * Msh[9] + uz * Msh[6]) + 2.0 * n * u2 * uz);
-  if (mom_out && lane == 0) {
-    double* o = mom_out + ((size_t)b * S + c) * 14;
-    o[0] = n;
-    o[1] = ux;
-    o[2] = uy;
-    o[3] = uz;
-    o[4] = T;
-    o[5] = Pxx;
-    o[6] = Pyy;
-    o[7] = Pzz;
-    o[8] = Pxy;
-    o[9] = Pxz;
-    o[10] = Pyz;
-    o[11] = qx;
-    o[12] = qy;
-    o[13] = qz;
-  }
+  const double qx = 0.5 * (M[10] - ux * M2 - 2.0 * (ux * M[4] + uy * M[7] + uz * M[8]) + 2.0 * n * u2 * ux);
+  const double qy = 0.5 * (M[11] - uy * M2 - 2.0 * (ux * M[7] + uy * M[5] + uz * M[9]) + 2.0 * n * u2 * uy);
+  const double qz = 0.5 * (M[12] - uz * M2 - 2.0 * (ux * M[8] + uy * M[9] + uz * M[6]) + 2.0 * n * u2 * uz);
   const bool bad = !(n > 0.0) || !(T > 0.0) || !isfinite(n + T + ux + uy + uz + qx + qy + qz);
-  if (bad) {
-    if (lane == 0) d.flags[b] = 1;
-  }
-  // relaxation time from mu = tau n T
-  double tau;
-  if (in.law == 0.0)
-    tau = in.kn * pow(T, in.omega - 1.0) / n;
-  else
-    tau = in.kn * (1.0 + in.suth) / (n * sqrt(T) * (1.0 + in.suth / T));
-  const double invtau = (in.collisionless != 0.0 || bad) ? 0.0 : 1.0 / tau;
-  const double Cs = (1.0 - in.pr) / (n * T * T);
-  double* rec = d.rec + ((size_t)b * S + c) * sh.rec_len;
-  if (lane == 0) {
+  double* sc = scal + lane * SC;
+  if (live) {
+    if (mom_out) {
+      double* o = mom_out + (size_t)g * 14;
+      o[0] = n;
+      o[1] = ux;
+      o[2] = uy;
+      o[3] = uz;
+      o[4] = T;
+      o[5] = Pxx;
+      o[6] = Pyy;
+      o[7] = Pzz;
+      o[8] = Pxy;
+      o[9] = Pxz;
+      o[10] = Pyz;
+      o[11] = qx;
+      o[12] = qy;
+      o[13] = qz;
+    }
+    if (bad) d.flags[b] = 1;
+    // relaxation time from mu = tau n T
+    double tau;
+    if (in->law == 0.0)
+      tau = in->kn * pow(T, in->omega - 1.0) / n;
+    else
+      tau = in->kn * (1.0 + in->suth) / (n * sqrt(T) * (1.0 + in->suth / T));
+    const double invtau = (in->collisionless != 0.0 || bad) ? 0.0 : 1.0 / tau;
+    const double Cs = (1.0 - in->pr) / (n * T * T);
+    double* rec = d.rec + (size_t)g * sh.rec_len;
     rec[0] = ux;
     rec[1] = uy;
     rec[2] = uz;
@@ -377,21 +420,49 @@ __global__ void __launch_bounds__(64) closure_kernel(Shape sh, DevPtrs d, const 
     rec[8] = qz;
     rec[9] = n;
     rec[10] = T;
+    // projection coefficients of the 1D Maxwellian factors (Sec. III)
+    double I[NX_MAX + 1], J[NX_MAX + 1], a[NYZ_MAX + 1];
+    const double Tc = bad ? 1.0 : T;
+    half_gauss_moments(ux, Tc, I);
+    half_projection(d.cx, sh.Nx, I, J);
+#pragma unroll
+    for (int l = 0; l <= NX_MAX; ++l)
+      if (l <= sh.Nx) sc[l] = n * J[l];
+    half_gauss_moments(-ux, Tc, I);
+    half_projection(d.cx, sh.Nx, I, J);
+#pragma unroll
+    for (int l = 0; l <= NX_MAX; ++l)
+      if (l <= sh.Nx) sc[oJm + l] = n * J[l];
+    full_coeffs(uy, Tc, a);
+#pragma unroll
+    for (int l = 0; l <= NYZ_MAX; ++l)
+      if (l <= sh.Ny) sc[oay + l] = a[l];
+    full_coeffs(uz, Tc, a);
+#pragma unroll
+    for (int l = 0; l <= NYZ_MAX; ++l)
+      if (l <= sh.Nz) sc[oaz + l] = a[l];
   }
-  // Hermite-projected equilibrium factors (Sec. III): n g_x on the 2Qx nodes, g_y g_z
-  double I[NX_MAX + 1], Jp[NX_MAX + 1], Jm[NX_MAX + 1];
-  const double Tc = bad ? 1.0 : T;
-  half_gauss_moments(ux, Tc, I);
-  half_projection(d.cx, sh.Nx, I, Jp);
-  half_gauss_moments(-ux, Tc, I);
-  half_projection(d.cx, sh.Nx, I, Jm);
-  for (int i = lane; i < 2 * sh.Qx; i += 64) rec[REC_HEAD + i] = n * gx_node(d.phix, sh.Qx, sh.Nx, i, Jp, Jm);
-  double ay[NYZ_MAX + 1], az[NYZ_MAX + 1];
-  full_coeffs(uy, Tc, ay);
-  full_coeffs(uz, Tc, az);
-  for (int jk = lane; jk < sh.QyQz; jk += 64) {
-    const int j = jk / sh.Qz, k = jk - j * sh.Qz;
-    rec[REC_HEAD + 2 * sh.Qx + jk] = full_node(d.phiy, sh.Ny, j, ay) * full_node(d.phiz, sh.Nz, k, az);
+  __syncthreads();
+  // 3) g_y and g_z of every node of the block, then the coalesced fill of the equilibrium
+  //    tables: n g_x on the 2Qx nodes and g_y g_z on the QyQz pairs
+  for (int idx = lane; idx < nblk_nodes * Qyz; idx += 64) {
+    const int nd = idx / Qyz, e = idx - nd * Qyz;
+    const double* sn = scal + nd * SC;
+    gyz[nd * Qyz + e] = (e < sh.Qy) ? full_node(phiy, sh.Ny, e, sn + oay) : full_node(phiz, sh.Nz, e - sh.Qy, sn + oaz);
+  }
+  __syncthreads();
+  const int nx2 = 2 * sh.Qx, E = nx2 + sh.QyQz;
+  for (int idx = lane; idx < nblk_nodes * E; idx += 64) {
+    const int nd = idx / E, e = idx - nd * E;
+    double val;
+    if (e < nx2) {
+      const double* sn = scal + nd * SC;
+      val = gx_node(phix, sh.Qx, sh.Nx, e, sn, sn + oJm);
+    } else {
+      const int jk = e - nx2, j = jk / sh.Qz, k = jk - j * sh.Qz;
+      val = gyz[nd * Qyz + j] * gyz[nd * Qyz + sh.Qy + k];
+    }
+    d.rec[(size_t)(g0 + nd) * sh.rec_len + REC_HEAD + e] = val;
   }
 }
 
@@ -400,13 +471,16 @@ __global__ void __launch_bounds__(64) closure_kernel(Shape sh, DevPtrs d, const 
 
 // value of node c for a thread's velocity before ghost completion: interior nodes are
 // loaded, nodes left of the centre line are the bounce-back images of nodes 1..3
-// (Eq. widetildei: F_{1-m; i j k} = F_{m; i~ j~ k}), nodes beyond the wall are 0 here
-__device__ __forceinline__ double raw_node(const double* __restrict__ Fb, int c, int S, int V, int v, int vm,
-                                           bool active) {
-  if (!active) return 0.0;
-  if (c >= 0 && c < S) return Fb[(size_t)c * V + v];
-  if (c < 0) return Fb[(size_t)(-c - 1) * V + vm];
-  return 0.0;
+// (Eq. widetildei: F_{1-m; i j k} = F_{m; i~ j~ k}), nodes beyond the wall are 0 here.
+// vcl is the thread's velocity clamped into [0, V).
+__device__ __forceinline__ double raw_node(const double* __restrict__ Fb, int c, int S, int V, int vcl, int vm) {
+  // branch- and select-free: every lane always issues one load from a valid address (nodes
+  // beyond the wall read node S-1; ghost_node replaces them), so the number of outstanding
+  // vector loads is the same on every path and prefetches stay in flight across iterations.
+  // Lanes beyond V read a valid velocity; their results are never stored or summed.
+  const int node = (c < 0) ? (-c - 1) : min(c, S - 1);
+  const int vel = (c < 0) ? vm : vcl;
+  return Fb[(size_t)node * V + vel];
 }
 
 // complete a node beyond the wall (App. A.4): p_x > 0 by quadratic extrapolation from the
@@ -457,8 +531,7 @@ __global__ void __launch_bounds__(256) stage_kernel(Shape sh, DevPtrs d, const d
 #pragma unroll
   for (int q = 0; q < 6; ++q) ex[q] = in->ex[q];
   const double ghost_in = active ? d.nw[b] * d.g_wall[(size_t)b * V + vv] : 0.0;
-  double a[16];
-  load_moment_operands(d.ptab, vb * blockDim.x + wave * 64, V, lane, a);
+  const int wave_v0 = vb * blockDim.x + wave * 64;
   const int s0 = ch * cs;
   const int nloc = min(cs, S - s0);
   const double* invdx = d.inv_dx + (size_t)b * S;
@@ -467,69 +540,105 @@ __global__ void __launch_bounds__(256) stage_kernel(Shape sh, DevPtrs d, const d
   double* part = d.partials + (((size_t)b * nvb + vb) * S + s0) * PART_STRIDE;
 
   // window W0..W5 = nodes c-2 .. c+3, first for c = s0 - 1
-  double W0 = raw_node(Fb, s0 - 3, S, V, v, vm, active);
-  double W1 = raw_node(Fb, s0 - 2, S, V, v, vm, active);
-  double W2 = raw_node(Fb, s0 - 1, S, V, v, vm, active);
-  double W3 = raw_node(Fb, s0, S, V, v, vm, active);
-  double W4 = raw_node(Fb, s0 + 1, S, V, v, vm, active);
-  double W5 = raw_node(Fb, s0 + 2, S, V, v, vm, active);
+  double W0 = raw_node(Fb, s0 - 3, S, V, vv, vm);
+  double W1 = raw_node(Fb, s0 - 2, S, V, vv, vm);
+  double W2 = raw_node(Fb, s0 - 1, S, V, vv, vm);
+  double W3 = raw_node(Fb, s0, S, V, vv, vm);
+  double W4 = raw_node(Fb, s0 + 1, S, V, vv, vm);
+  double W5 = raw_node(Fb, s0 + 2, S, V, vv, vm);
   W3 = ghost_node(W3, s0, S, pos, W2, W1, W0, ex, ghost_in);
   W4 = ghost_node(W4, s0 + 1, S, pos, W3, W2, W1, ex, ghost_in);
   W5 = ghost_node(W5, s0 + 2, S, pos, W4, W3, W2, ex, ghost_in);
   double fl = stencil_flux<SCHEME>(pos, px, W0, W1, W2, W3, W4, W5);
-  double nxt = raw_node(Fb, s0 + 3, S, V, v, vm, active);
+
+  // Per-node operands, software-pipelined two nodes ahead in two alternating register
+  // sets (the node loop is unrolled by two, so no register with a load in flight is ever
+  // copied).  All are unconditional vector loads, which complete in order: the window node
+  // c+3, F_l, the two equilibrium-factor gathers, and the node's uniform closure scalars
+  // (lane q < 9 loads record field q: u, 1/tau, Shakhov coefficients, q; lane 9 loads
+  // 1/dx), broadcast with readlane where used.
+  struct Ops {
+    double raw, fl0, gx, gyz, sc;
+  };
+  const int clast = s0 + nloc - 1;
+  const int gx_off = REC_HEAD + i, gyz_off = REC_HEAD + 2 * Qx + jk;
+  const int sq = lane < 9 ? lane : 0;
+  auto ld_ops = [&](int c, Ops& o) {
+    const int cc = min(c, clast);
+    const double* rec = recb + (size_t)cc * sh.rec_len;
+    o.raw = raw_node(Fb, c + 3, S, V, vv, vm);
+    if constexpr (STAGE != 1)
+      o.fl0 = Fl[base + (size_t)cc * V + vv];
+    else
+      o.fl0 = 0.0;
+    o.gx = rec[gx_off];
+    o.gyz = rec[gyz_off];
+    const double* sp = (lane == 9) ? invdx + cc : rec + sq;
+    o.sc = *sp;
+  };
   double rd = 0.0, rf = 0.0;
+  double* junk = d.junk + threadIdx.x;  // store target of lanes beyond V
+  // one node: complete the window, flux, collision, RK combine, store; returns F_out
+  auto node = [&](int c, const Ops& o) -> double {
+    const double Wn = ghost_node(o.raw, c + 3, S, pos, W5, W4, W3, ex, ghost_in);
+    W0 = W1;
+    W1 = W2;
+    W2 = W3;
+    W3 = W4;
+    W4 = W5;
+    W5 = Wn;
+    const double scc = o.sc;
+    const double fr = stencil_flux<SCHEME>(pos, px, W0, W1, W2, W3, W4, W5);
+    const double D = (fr - fl) * bcast(scc, 9);  // Eq. flux
+    fl = fr;
+    const double F = W2;
+    const double feq = o.gx * o.gyz;
+    const double Cs = bcast(scc, 4);
+    double FS = feq;
+    if (Cs != 0.0) {
+      const double xx = px - bcast(scc, 0), xy = py - bcast(scc, 1), xz = pz - bcast(scc, 2);
+      const double xi2 = xx * xx + xy * xy + xz * xz;
+      const double qxi = bcast(scc, 6) * xx + bcast(scc, 7) * xy + bcast(scc, 8) * xz;
+      FS = feq + feq * ((bcast(scc, 5) * xi2 - Cs) * qxi);  // F^eq (1 + S), Eq. sdef
+    }
+    const double G = F + dt * ((FS - F) * bcast(scc, 3) - D);  // F + dt L[F], Eq. L_def
+    double out;
+    if constexpr (STAGE == 1) {
+      out = G;
+    } else if constexpr (STAGE == 2) {
+      out = 0.75 * o.fl0 + 0.25 * G;
+    } else {
+      out = (1.0 / 3.0) * o.fl0 + (2.0 / 3.0) * G;
+      const double dlt = active ? out - o.fl0 : 0.0;
+      const double flm = active ? o.fl0 : 0.0;
+      rd += dlt * dlt;
+      rf += flm * flm;
+    }
+    double* dst = active ? Fout + base + (size_t)c * V + v : junk;
+    *dst = out;
+    return active ? out : 0.0;
+  };
+  Ops A, Bo;
+  ld_ops(s0, A);
+  ld_ops(s0 + 1, Bo);
 
   for (int g = 0; g < nloc; g += 16) {
     const int cnt = min(16, nloc - g);
-    for (int u = 0; u < 16; ++u) {
-      double out = 0.0;
-      if (u < cnt) {
-        const int c = s0 + g + u;
-        const double Wn = ghost_node(nxt, c + 3, S, pos, W5, W4, W3, ex, ghost_in);
-        nxt = raw_node(Fb, c + 4, S, V, v, vm, active);  // prefetch the next window node
-        W0 = W1;
-        W1 = W2;
-        W2 = W3;
-        W3 = W4;
-        W4 = W5;
-        W5 = Wn;
-        double fl0 = 0.0;
-        if constexpr (STAGE != 1) fl0 = active ? Fl[base + (size_t)c * V + v] : 0.0;
-        const double fr = stencil_flux<SCHEME>(pos, px, W0, W1, W2, W3, W4, W5);
-        const double D = (fr - fl) * invdx[c];  // Eq. flux
-        fl = fr;
-        const double F = W2;
-        const double* rec = recb + (size_t)c * sh.rec_len;
-        const double feq = rec[REC_HEAD + i] * rec[REC_HEAD + 2 * Qx + jk];
-        const double Cs = rec[4];
-        double FS = feq;
-        if (Cs != 0.0) {
-          const double xx = px - rec[0], xy = py - rec[1], xz = pz - rec[2];
-          const double xi2 = xx * xx + xy * xy + xz * xz;
-          const double qxi = rec[6] * xx + rec[7] * xy + rec[8] * xz;
-          FS = feq + feq * ((rec[5] * xi2 - Cs) * qxi);  // F^eq (1 + S), Eq. sdef
-        }
-        const double G = F + dt * ((FS - F) * rec[3] - D);  // F + dt L[F], Eq. L_def
-        if constexpr (STAGE == 1) {
-          out = G;
-        } else if constexpr (STAGE == 2) {
-          out = 0.75 * fl0 + 0.25 * G;
-        } else {
-          out = (1.0 / 3.0) * fl0 + (2.0 / 3.0) * G;
-          const double dlt = active ? out - fl0 : 0.0;
-          rd += dlt * dlt;
-          rf += fl0 * fl0;
-        }
-        if (active) {
-          Fout[base + (size_t)c * V + v] = out;
-        } else {
-          out = 0.0;
-        }
-      }
-      ft[u * FT_LD + lane] = out;
+    int u = 0;
+    for (; u + 1 < cnt; u += 2) {
+      const int c = s0 + g + u;
+      ft[u * FT_LD + lane] = node(c, A);
+      ld_ops(c + 2, A);
+      ft[(u + 1) * FT_LD + lane] = node(c + 1, Bo);
+      ld_ops(c + 3, Bo);
     }
-    flush_group(lds_ft, lds_red, a, wave, waves, lane, cnt, part + (size_t)g * PART_STRIDE);
+    if (u < cnt) {
+      // odd count: only at the end of the chunk (groups before the last hold 16 nodes)
+      ft[u * FT_LD + lane] = node(s0 + g + u, A);
+      ++u;
+    }
+    for (; u < 16; ++u) ft[u * FT_LD + lane] = 0.0;
+    flush_group(lds_ft, lds_red, d.ptab, wave_v0, V, wave, waves, lane, cnt, part + (size_t)g * PART_STRIDE);
     __syncthreads();
   }
   if constexpr (STAGE == 3) {
@@ -601,8 +710,17 @@ int launch_partials(const Shape& sh, const DevPtrs& d, const double* F, int cell
 }
 
 int launch_closure(const Shape& sh, const DevPtrs& d, const double* Fin, int nvb, double* mom_out, void* stream) {
-  hipLaunchKernelGGL(closure_kernel, dim3(sh.B * (sh.S + 1)), dim3(64), 0, (hipStream_t)stream, sh, d, Fin, nvb,
-                     mom_out);
+  // nodes per block: up to 64, fewer when there are few nodes, so the grid keeps
+  // several hundred blocks
+  const int total = sh.B * sh.S;
+  int nb = CL_NODES;
+  while (nb > 4 && (total + nb - 1) / nb < 1024) nb >>= 1;
+  const int node_blocks = (total + nb - 1) / nb;
+  const size_t lds = ((size_t)nb * PART_STRIDE + (size_t)nb * (2 * (sh.Nx + 1) + sh.Ny + sh.Nz + 2) +
+                      (size_t)sh.Qx * (sh.Nx + 1) + (size_t)sh.Qy * (sh.Ny + 1) + (size_t)sh.Qz * (sh.Nz + 1) +
+                      (size_t)nb * (sh.Qy + sh.Qz)) * sizeof(double);
+  hipLaunchKernelGGL(closure_kernel, dim3(node_blocks + sh.B), dim3(64), lds, (hipStream_t)stream, sh, d, Fin, nvb,
+                     mom_out, node_blocks, nb);
   return (int)hipGetLastError();
 }
 
