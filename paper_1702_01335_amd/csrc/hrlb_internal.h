@@ -59,7 +59,7 @@ struct DevPtrs {
   double* g_rest;     // [B][V]  discrete equilibrium at rest per unit density
   double* g_wall;     // [B][V]  wall Maxwellian per unit density
   // per step / stage
-  double* partials;   // [B][nvb][S][PART_STRIDE]
+  double* partials;   // [B][S][nvb][PART_STRIDE] (node-major)
   double* rec;        // [B][S][rec_len]
   double* nw;         // [B]
   double* resid_part; // [B][nres][2]

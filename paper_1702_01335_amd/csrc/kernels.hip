@@ -252,7 +252,7 @@ __device__ __forceinline__ dbl4 moment_mfma(const double* ft, const double* a, i
 // the block's waves and write the block's partials for nodes s .. s+cnt-1.
 __device__ __forceinline__ void flush_group(double* lds_ft, double* lds_red, const double* __restrict__ ptab,
                                             int wave_v0, int V, int wave, int waves, int lane, int cnt,
-                                            double* __restrict__ out) {
+                                            double* __restrict__ out, int node_stride) {
   double a[16];
   load_moment_operands(ptab, wave_v0, V, lane, a);
   __syncthreads();
@@ -267,7 +267,7 @@ __device__ __forceinline__ void flush_group(double* lds_ft, double* lds_red, con
     const int n = idx / NMOM, q = idx - n * NMOM;
     double s = 0.0;
     for (int w = 0; w < waves; ++w) s += lds_red[w * RED_WAVE + n * 16 + q];
-    out[(size_t)n * PART_STRIDE + q] = s;
+    out[(size_t)n * node_stride + q] = s;
   }
 }
 
@@ -289,11 +289,13 @@ __global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, cons
   const int nloc = min(cs, S - s0);
   const double* Fb = F + (size_t)b * S * V;
   double* ft = lds_ft + wave * FT_WAVE;
-  double* part = d.partials + (((size_t)b * nvb + vb) * S + s0) * PART_STRIDE;
+  // partials are node-major, [b][S][nvb][16]
+  const int nstride = nvb * PART_STRIDE;
+  double* part = d.partials + (((size_t)b * S + s0) * nvb + vb) * PART_STRIDE;
   for (int g = 0; g < nloc; g += 16) {
     const int cnt = min(16, nloc - g);
     for (int u = 0; u < 16; ++u) ft[u * FT_LD + lane] = (u < cnt && active) ? Fb[(size_t)(s0 + g + u) * V + v] : 0.0;
-    flush_group(lds_ft, lds_red, d.ptab, wave_v0, V, wave, waves, lane, cnt, part + (size_t)g * PART_STRIDE);
+    flush_group(lds_ft, lds_red, d.ptab, wave_v0, V, wave, waves, lane, cnt, part + (size_t)g * nstride, nstride);
     __syncthreads();
   }
 }
@@ -350,16 +352,24 @@ __global__ void __launch_bounds__(64) closure_kernel(Shape sh, DevPtrs d, const 
   for (int e = lane; e < nphx; e += 64) phix[e] = d.phix[e];
   for (int e = lane; e < nphy; e += 64) phiy[e] = d.phiy[e];
   for (int e = lane; e < nphz; e += 64) phiz[e] = d.phiz[e];
-  // 1) sum the moment partials over velocity blocks: the block's [node][16] tile is read
-  //    with consecutive lanes on consecutive doubles
+  // 1) sum the moment partials over velocity blocks.  They are node-major ([node][nvb][16]),
+  //    so the block's nodes are one contiguous range; a thread owns (node, moment) pairs
+  //    and sums their nvb entries with four independent accumulators in flight
   for (int e = lane; e < nblk_nodes * PART_STRIDE; e += 64) {
     const int nd = e >> 4, q = e & 15;
-    const int g = g0 + nd, b = g / S, c = g - b * S;
-    const double* src = d.partials + ((size_t)b * nvb * S + c) * PART_STRIDE + q;
-    double acc = 0.0;
-    if (q < NMOM)
-      for (int vb = 0; vb < nvb; ++vb) acc += src[(size_t)vb * S * PART_STRIDE];
-    msum[e] = acc;
+    const double* src = d.partials + (size_t)(g0 + nd) * nvb * PART_STRIDE + q;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (q < NMOM) {
+      int vb = 0;
+      for (; vb + 3 < nvb; vb += 4) {
+        a0 += src[(size_t)vb * PART_STRIDE];
+        a1 += src[(size_t)(vb + 1) * PART_STRIDE];
+        a2 += src[(size_t)(vb + 2) * PART_STRIDE];
+        a3 += src[(size_t)(vb + 3) * PART_STRIDE];
+      }
+      for (; vb < nvb; ++vb) a0 += src[(size_t)vb * PART_STRIDE];
+    }
+    msum[e] = (a0 + a1) + (a2 + a3);
   }
   __syncthreads();
   // 2) one lane per node: moments, tau, Shakhov coefficients, projection coefficients
@@ -537,7 +547,9 @@ __global__ void __launch_bounds__(256) stage_kernel(Shape sh, DevPtrs d, const d
   const double* invdx = d.inv_dx + (size_t)b * S;
   const double* recb = d.rec + (size_t)b * S * sh.rec_len;
   double* ft = lds_ft + wave * FT_WAVE;
-  double* part = d.partials + (((size_t)b * nvb + vb) * S + s0) * PART_STRIDE;
+  // partials are node-major, [b][S][nvb][16]
+  const int nstride = nvb * PART_STRIDE;
+  double* part = d.partials + (((size_t)b * S + s0) * nvb + vb) * PART_STRIDE;
 
   // window W0..W5 = nodes c-2 .. c+3, first for c = s0 - 1
   double W0 = raw_node(Fb, s0 - 3, S, V, vv, vm);
@@ -638,7 +650,7 @@ __global__ void __launch_bounds__(256) stage_kernel(Shape sh, DevPtrs d, const d
       ++u;
     }
     for (; u < 16; ++u) ft[u * FT_LD + lane] = 0.0;
-    flush_group(lds_ft, lds_red, d.ptab, wave_v0, V, wave, waves, lane, cnt, part + (size_t)g * PART_STRIDE);
+    flush_group(lds_ft, lds_red, d.ptab, wave_v0, V, wave, waves, lane, cnt, part + (size_t)g * nstride, nstride);
     __syncthreads();
   }
   if constexpr (STAGE == 3) {
@@ -714,7 +726,7 @@ int launch_closure(const Shape& sh, const DevPtrs& d, const double* Fin, int nvb
   // several hundred blocks
   const int total = sh.B * sh.S;
   int nb = CL_NODES;
-  while (nb > 4 && (total + nb - 1) / nb < 1024) nb >>= 1;
+  while (nb > 4 && (total + nb - 1) / nb < 4096) nb >>= 1;
   const int node_blocks = (total + nb - 1) / nb;
   const size_t lds = ((size_t)nb * PART_STRIDE + (size_t)nb * (2 * (sh.Nx + 1) + sh.Ny + sh.Nz + 2) +
                       (size_t)sh.Qx * (sh.Nx + 1) + (size_t)sh.Qy * (sh.Ny + 1) + (size_t)sh.Qz * (sh.Nz + 1) +
