@@ -75,6 +75,22 @@ def time_steps(solver, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall
 
 
+def profiled_traffic(tag, bytes_per_launch):
+    """HBM bytes per stage-kernel launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    passes (profiles/<tag>_traffic.json), or None when the kernel source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, 'profiles', f'{tag}_traffic.json')
+    if not os.path.exists(path):
+        return None
+    tr = json.load(open(path))
+    src = open(os.path.join(ROOT, 'paper_1702_01335_amd', 'csrc', 'kernels.hip'), 'rb').read()
+    if hashlib.sha256(src).hexdigest() != tr['kernel_source_sha256']:
+        return None
+    ks = tr['stage_kernels'].values()
+    t = sum(k['fetch_bytes'] + k['write_bytes'] for k in ks) / len(ks)
+    return {'bytes_per_launch': t, 'over_algorithmic': t / bytes_per_launch, 'source': f'profiles/{tag}.md'}
+
+
 def cpu_baseline(wl, seconds):
     """The oracle (numpy, FP64, single-threaded) on one instance of the workload for a
     bounded number of steps; returns pair-updates per second."""
@@ -125,6 +141,7 @@ def main():
     closure_avg_s = tm['closure_ms'] / tm['closure_launches'] * 1e-3
     bytes_per_launch = pairs * BYTES_PER_PAIR_STEP / 3.0
     achieved = bytes_per_launch / stage_avg_s
+    traffic = profiled_traffic(f"stage_kernel_{args.workload}_b{args.batch}", bytes_per_launch)
     res = solver.residual()
 
     if args.copy_probe_mib:
@@ -163,7 +180,9 @@ def main():
                    'parallelism': 'single GPU'},
         'hbm_frac_step': pairs * BYTES_PER_PAIR_STEP / (ms * 1e-3) / HBM_PEAK,
         'roofline': {'bound': 'hbm', 'achieved': achieved / 1e9, 'peak': HBM_PEAK / 1e9, 'unit': 'GB/s',
-                     'frac': achieved / HBM_PEAK, 'traffic': None,
+                     'frac': achieved / HBM_PEAK,
+                     'traffic': traffic['bytes_per_launch'] if traffic else None, 'traffic_unit': 'bytes/launch',
+                     'traffic_detail': traffic,
                      'kernel': 'stage_kernel', 'avg_launch_us': stage_avg_s * 1e6,
                      'bytes_per_launch': bytes_per_launch, 'closure_avg_us': closure_avg_s * 1e6},
         'single_instance': single,
