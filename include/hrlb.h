@@ -65,6 +65,7 @@ typedef struct hrlb_params {
 
 typedef struct hrlb_quad hrlb_quad;
 typedef struct hrlb_sim hrlb_sim;
+typedef struct hrlb_batch hrlb_batch;
 
 /* Message for the calling thread's last failed call ("" if none). Owned by the library. */
 const char* hrlb_last_error(void);
@@ -183,6 +184,34 @@ int hrlb_set_graph(hrlb_sim* sim, int on);
  */
 int hrlb_set_timing(hrlb_sim* sim, int on);
 int hrlb_get_timing(hrlb_sim* sim, double* ms, long long* launches);
+
+/*
+ * Batches: advance several sims -- each a group of instances sharing one velocity set,
+ * node count and scheme, the groups differing in any of them -- together, with one
+ * persistent launch per kernel per RK3 stage.  The launches walk device-side tables of
+ * (group, instance, velocity block, node chunk) tiles and of closure work items; one RK3
+ * step of the whole batch is captured as a HIP graph on first use and replayed.  Results
+ * are those of stepping every sim alone with the same launch shape, bit for bit.
+ *
+ * batch_bytes: device bytes of the batch's tables (caller-owned, 256-byte aligned).
+ * batch_create: `cells` nodes per thread and `waves` waves per workgroup for every group
+ *   (each sim's launch shape is set to it); enqueues on `stream` and synchronises it.  The
+ *   sims must stay alive and must not be stepped on their own while the batch is in use.
+ * batch_step: nsteps RK3 steps of every active instance (asynchronous).
+ * batch_residual: synchronise; h_out[i] is the residual of concatenated instance i (the
+ *   instances of sims[0], then sims[1], ...); HRLB_ENUMERIC as for hrlb_residual.
+ * batch_set_active: active[i] = 0 retires instance i (its state stops advancing; it can be
+ *   re-activated); rewrites the tile table; synchronises the stream.
+ * Errors: HRLB_EINVAL, HRLB_ENOMEM, HRLB_EHIP, HRLB_ENUMERIC.
+ */
+int hrlb_batch_bytes(hrlb_sim* const* sims, int nsims, int cells, int waves, size_t* bytes);
+int hrlb_batch_create(hrlb_sim* const* sims, int nsims, int cells, int waves, void* d_work, size_t work_bytes,
+                      void* stream, hrlb_batch** out);
+int hrlb_batch_step(hrlb_batch* batch, int nsteps);
+int hrlb_batch_residual(hrlb_batch* batch, double* h_out);
+int hrlb_batch_set_active(hrlb_batch* batch, const int* active);
+int hrlb_batch_info(const hrlb_batch* batch, int* ntiles, int* nitems, int* grid_stage, int* grid_closure);
+void hrlb_batch_free(hrlb_batch* batch);
 
 #ifdef __cplusplus
 }

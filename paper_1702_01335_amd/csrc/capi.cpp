@@ -64,6 +64,24 @@ struct hrlb_sim {
   long long launches[2];
 };
 
+struct hrlb_batch {
+  std::vector<hrlb_sim*> sims;
+  std::vector<int> inst_offset;   // first concatenated instance index of each sim
+  int cells, waves;
+  hipStream_t stream;
+  GroupDesc* d_groups;
+  int* d_tiles;      // int4 per tile
+  int* d_ntiles;
+  int* d_items;      // int2 per closure item
+  int* d_nitems;
+  int max_tiles, max_items, ntiles, nitems;
+  int grid_stage, grid_closure;
+  size_t lds_stage, lds_closure;
+  std::vector<int> active;
+  hipGraphExec_t gexec;
+  hipStream_t cap_stream;
+};
+
 namespace hrlb {
 
 WorkLayout work_layout(const Shape& sh) {
@@ -546,6 +564,247 @@ int hrlb_autotune(hrlb_sim* s, int probe_steps, const char* cache_path, int* bes
     f << "{\"key\": \"" << key << "\", \"cells\": " << bc << ", \"waves\": " << bw << ", \"ms\": " << best << "}\n";
   }
   return HRLB_OK;
+}
+
+// ---- batches of sims (ragged sweeps) ---------------------------------------------------
+
+static void batch_sizes(hrlb_sim* const* sims, int nsims, int cells, int waves, int* max_tiles, int* max_items) {
+  long long t = 0, it = 0;
+  for (int k = 0; k < nsims; ++k) {
+    const Shape& sh = sims[k]->sh;
+    const int nvb = (sh.V + 64 * waves - 1) / (64 * waves), nch = (sh.S + cells - 1) / cells;
+    t += (long long)sh.B * nvb * nch;
+    const int total = sh.B * sh.S, nb = closure_nodes_for(total);
+    it += (total + nb - 1) / nb + sh.B;
+  }
+  *max_tiles = (int)t;
+  *max_items = (int)it;
+}
+
+static size_t batch_bytes_of(int nsims, int max_tiles, int max_items) {
+  return align256(nsims * sizeof(GroupDesc)) + align256((size_t)max_tiles * 4 * sizeof(int)) + 256 +
+         align256((size_t)max_items * 2 * sizeof(int)) + 256;
+}
+
+static int batch_check(hrlb_sim* const* sims, int nsims, int cells, int waves) {
+  if (!sims || nsims < 1) return fail(HRLB_EINVAL, "batch: need at least one sim");
+  for (int k = 0; k < nsims; ++k)
+    if (!sims[k]) return fail(HRLB_EINVAL, "batch: NULL sim");
+  if (cells < 1 || cells > 4096) return fail(HRLB_EINVAL, "batch: cells must be in 1..4096");
+  if (waves < 1 || waves > MAX_WAVES) return fail(HRLB_EINVAL, "batch: waves must be in 1..4");
+  return HRLB_OK;
+}
+
+int hrlb_batch_bytes(hrlb_sim* const* sims, int nsims, int cells, int waves, size_t* bytes) {
+  if (!bytes) return fail(HRLB_EINVAL, "batch_bytes: NULL argument");
+  int rc = batch_check(sims, nsims, cells, waves);
+  if (rc != HRLB_OK) return rc;
+  int mt, mi;
+  batch_sizes(sims, nsims, cells, waves, &mt, &mi);
+  *bytes = batch_bytes_of(nsims, mt, mi);
+  return HRLB_OK;
+}
+
+// rewrite the tile table from the active flags (stream-ordered upload, then synchronise so
+// the host staging vector may be released)
+static int batch_upload_tiles(hrlb_batch* bt) {
+  std::vector<int> tiles;
+  tiles.reserve((size_t)bt->max_tiles * 4);
+  for (size_t k = 0; k < bt->sims.size(); ++k) {
+    const Shape& sh = bt->sims[k]->sh;
+    const int nvb = (sh.V + 64 * bt->waves - 1) / (64 * bt->waves), nch = (sh.S + bt->cells - 1) / bt->cells;
+    for (int b = 0; b < sh.B; ++b) {
+      if (!bt->active[bt->inst_offset[k] + b]) continue;
+      for (int vb = 0; vb < nvb; ++vb)
+        for (int ch = 0; ch < nch; ++ch) {
+          tiles.push_back((int)k);
+          tiles.push_back(b);
+          tiles.push_back(vb);
+          tiles.push_back(ch);
+        }
+    }
+  }
+  bt->ntiles = (int)(tiles.size() / 4);
+  if (!tiles.empty())
+    HIP_TRY(hipMemcpyAsync(bt->d_tiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, bt->stream),
+            "batch: tile upload");
+  HIP_TRY(hipMemcpyAsync(bt->d_ntiles, &bt->ntiles, sizeof(int), hipMemcpyHostToDevice, bt->stream), "batch: tile upload");
+  HIP_TRY(hipStreamSynchronize(bt->stream), "batch: tile upload");
+  return HRLB_OK;
+}
+
+int hrlb_batch_create(hrlb_sim* const* sims, int nsims, int cells, int waves, void* d_work, size_t work_bytes,
+                      void* stream, hrlb_batch** out) {
+  if (!out) return fail(HRLB_EINVAL, "batch_create: out is NULL");
+  *out = nullptr;
+  int rc = batch_check(sims, nsims, cells, waves);
+  if (rc != HRLB_OK) return rc;
+  if (!d_work || ((uintptr_t)d_work & 255)) return fail(HRLB_EINVAL, "batch_create: work buffer NULL or misaligned");
+  int mt, mi;
+  batch_sizes(sims, nsims, cells, waves, &mt, &mi);
+  if (work_bytes < batch_bytes_of(nsims, mt, mi)) return fail(HRLB_ENOMEM, "batch_create: work buffer too small");
+  for (int a = 0; a < nsims; ++a)
+    for (int b = a + 1; b < nsims; ++b)
+      if (sims[a] == sims[b]) return fail(HRLB_EINVAL, "batch_create: a sim appears twice");
+  hrlb_batch* bt = new hrlb_batch;
+  bt->sims.assign(sims, sims + nsims);
+  bt->cells = cells;
+  bt->waves = waves;
+  bt->stream = (hipStream_t)stream;
+  bt->max_tiles = mt;
+  bt->max_items = mi;
+  bt->gexec = nullptr;
+  bt->cap_stream = nullptr;
+  char* w = (char*)d_work;
+  bt->d_groups = (GroupDesc*)w;
+  w += align256(nsims * sizeof(GroupDesc));
+  bt->d_tiles = (int*)w;
+  w += align256((size_t)mt * 4 * sizeof(int));
+  bt->d_ntiles = (int*)w;
+  w += 256;
+  bt->d_items = (int*)w;
+  w += align256((size_t)mi * 2 * sizeof(int));
+  bt->d_nitems = (int*)w;
+  std::vector<GroupDesc> groups(nsims);
+  std::vector<int> items;
+  int total_inst = 0;
+  bt->lds_closure = 0;
+  for (int k = 0; k < nsims; ++k) {
+    hrlb_sim* sm = sims[k];
+    // every instance of the group advances with the batch's launch shape; re-lay the
+    // moment partials of the current state accordingly (on the batch's stream)
+    hipError_t e = (hipError_t)launch_partials(sm->sh, sm->d, sm->d.F[0], cells, waves, bt->stream);
+    if (e != hipSuccess) {
+      delete bt;
+      return hip_fail(e, "batch_create: partials");
+    }
+    sm->cells = cells;
+    sm->waves = waves;
+    GroupDesc& g = groups[k];
+    std::memset(&g, 0, sizeof(g));
+    g.sh = sm->sh;
+    g.d = sm->d;
+    g.nvb = (sm->sh.V + 64 * waves - 1) / (64 * waves);
+    g.nch = (sm->sh.S + cells - 1) / cells;
+    g.cs = cells;
+    const int total = sm->sh.B * sm->sh.S;
+    g.nb = closure_nodes_for(total);
+    g.node_blocks = (total + g.nb - 1) / g.nb;
+    sm->part_nvb = g.nvb;
+    for (int it = 0; it < g.node_blocks + sm->sh.B; ++it) {
+      items.push_back(k);
+      items.push_back(it);
+    }
+    bt->lds_closure = std::max(bt->lds_closure, closure_lds_bytes_for(sm->sh, g.nb));
+    bt->inst_offset.push_back(total_inst);
+    total_inst += sm->sh.B;
+  }
+  bt->active.assign(total_inst, 1);
+  bt->nitems = (int)(items.size() / 2);
+  bt->lds_stage = stage_lds_bytes_for(waves);
+  hipError_t e = hipMemcpyAsync(bt->d_groups, groups.data(), nsims * sizeof(GroupDesc), hipMemcpyHostToDevice, bt->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(bt->d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, bt->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(bt->d_nitems, &bt->nitems, sizeof(int), hipMemcpyHostToDevice, bt->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);
+  if (e != hipSuccess) {
+    delete bt;
+    return hip_fail(e, "batch_create: upload");
+  }
+  if ((rc = batch_upload_tiles(bt)) != HRLB_OK) {
+    delete bt;
+    return rc;
+  }
+  int dev = 0, ncu = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  // persistent grids: a few resident blocks per CU loop over the tables
+  bt->grid_stage = std::max(1, std::min(mt, ncu * 16 / waves));
+  bt->grid_closure = std::max(1, std::min(mi, ncu * 8));
+  *out = bt;
+  return HRLB_OK;
+}
+
+static hipError_t batch_enqueue_step(hrlb_batch* bt, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (int stage = 1; stage <= 3 && e == hipSuccess; ++stage) {
+    e = (hipError_t)launch_batch_closure(stage, bt->d_groups, bt->d_items, bt->d_nitems, bt->grid_closure,
+                                         bt->lds_closure, st);
+    if (e == hipSuccess)
+      e = (hipError_t)launch_batch_stage(stage, bt->d_groups, bt->d_tiles, bt->d_ntiles, bt->grid_stage, bt->waves,
+                                         bt->lds_stage, st);
+  }
+  return e;
+}
+
+int hrlb_batch_step(hrlb_batch* bt, int nsteps) {
+  if (!bt) return fail(HRLB_EINVAL, "batch_step: batch is NULL");
+  if (nsteps < 0) return fail(HRLB_EINVAL, "batch_step: nsteps must be >= 0");
+  if (nsteps == 0) return HRLB_OK;
+  if (!bt->gexec) {
+    hipError_t e = hipSuccess;
+    if (!bt->cap_stream) e = hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking);
+    hipGraph_t g = nullptr;
+    if (e == hipSuccess) e = hipStreamBeginCapture(bt->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t el = batch_enqueue_step(bt, bt->cap_stream);
+      e = hipStreamEndCapture(bt->cap_stream, &g);
+      if (el != hipSuccess) e = el;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&bt->gexec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "batch_step: graph capture");
+  }
+  for (int n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(bt->gexec, bt->stream), "batch_step: graph launch");
+  for (hrlb_sim* sm : bt->sims) {
+    const int nvb = (sm->sh.V + 64 * bt->waves - 1) / (64 * bt->waves), nch = (sm->sh.S + bt->cells - 1) / bt->cells;
+    sm->part_nvb = nvb;
+    sm->resid_nres = nvb * nch;
+  }
+  return HRLB_OK;
+}
+
+int hrlb_batch_residual(hrlb_batch* bt, double* h_out) {
+  if (!bt || !h_out) return fail(HRLB_EINVAL, "batch_residual: NULL argument");
+  std::vector<int> flags(bt->active.size());
+  for (size_t k = 0; k < bt->sims.size(); ++k) {
+    hrlb_sim* sm = bt->sims[k];
+    if (sm->resid_nres > 0) {
+      hipError_t e = (hipError_t)launch_residual(sm->sh, sm->d, sm->resid_nres, bt->stream);
+      if (e != hipSuccess) return hip_fail(e, "batch_residual: launch");
+    }
+    const int o = bt->inst_offset[k];
+    HIP_TRY(hipMemcpyAsync(h_out + o, sm->d.resid, sm->sh.B * sizeof(double), hipMemcpyDeviceToHost, bt->stream),
+            "batch_residual: copy");
+    HIP_TRY(hipMemcpyAsync(flags.data() + o, sm->d.flags, sm->sh.B * sizeof(int), hipMemcpyDeviceToHost, bt->stream),
+            "batch_residual: copy");
+  }
+  HIP_TRY(hipStreamSynchronize(bt->stream), "batch_residual: synchronize");
+  for (size_t i = 0; i < flags.size(); ++i)
+    if (flags[i]) return fail(HRLB_ENUMERIC, "batch_residual: instance " + std::to_string(i) + " met n <= 0, T <= 0 or a non-finite moment");
+  return HRLB_OK;
+}
+
+int hrlb_batch_set_active(hrlb_batch* bt, const int* active) {
+  if (!bt || !active) return fail(HRLB_EINVAL, "batch_set_active: NULL argument");
+  for (size_t i = 0; i < bt->active.size(); ++i) bt->active[i] = active[i] ? 1 : 0;
+  return batch_upload_tiles(bt);
+}
+
+int hrlb_batch_info(const hrlb_batch* bt, int* ntiles, int* nitems, int* grid_stage, int* grid_closure) {
+  if (!bt || !ntiles || !nitems || !grid_stage || !grid_closure) return fail(HRLB_EINVAL, "batch_info: NULL argument");
+  *ntiles = bt->ntiles;
+  *nitems = bt->nitems;
+  *grid_stage = bt->grid_stage;
+  *grid_closure = bt->grid_closure;
+  return HRLB_OK;
+}
+
+void hrlb_batch_free(hrlb_batch* bt) {
+  if (!bt) return;
+  if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
+  if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
+  delete bt;
 }
 
 int hrlb_set_graph(hrlb_sim* s, int on) {

@@ -77,6 +77,15 @@ struct Shape {
   int rec_len;        // REC_HEAD + 2 Qx + Qy Qz, rounded up to even
 };
 
+// One uniform group (one sim) inside a batch, as the batched kernels see it.
+struct GroupDesc {
+  Shape sh;
+  DevPtrs d;
+  int nvb, nch, cs;        // stage-kernel tiling (waves per block is the batch's)
+  int node_blocks, nb;     // closure work split: node blocks of nb nodes, then B wall items
+  int pad[3];
+};
+
 // Work-buffer carve-up; returns the total bytes and fills offsets.
 struct WorkLayout {
   size_t px, py, pz, phix, cx, phiy, phiz, ptab, inst, inv_dx, g_rest, g_wall, partials, rec, nw, resid_part,
@@ -93,5 +102,16 @@ int launch_closure(const Shape& sh, const DevPtrs& d, const double* Fin, int nvb
 int launch_stage(const Shape& sh, const DevPtrs& d, int stage, const double* Fin, const double* Fl, double* Fout,
                  int cells, int waves, void* stream);
 int launch_residual(const Shape& sh, const DevPtrs& d, int nres, void* stream);
+
+// batched launches over several groups: tiles are int4 (group, instance, vblock, chunk),
+// closure items int2 (group, block); counts live in device memory so a captured graph
+// keeps working when the tables are rewritten
+int launch_batch_stage(int stage, const GroupDesc* groups, const void* tiles, const int* ntiles, int grid, int waves,
+                       size_t lds_bytes, void* stream);
+int launch_batch_closure(int stage, const GroupDesc* groups, const void* items, const int* nitems, int grid,
+                         size_t lds_bytes, void* stream);
+size_t stage_lds_bytes_for(int waves);
+size_t closure_lds_bytes_for(const Shape& sh, int nb);
+int closure_nodes_for(int total_nodes);
 
 }  // namespace hrlb

@@ -306,14 +306,17 @@ __global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, cons
 
 constexpr int CL_NODES = 64;             // most nodes per closure block
 
-__global__ void __launch_bounds__(64) closure_kernel(Shape sh, DevPtrs d, const double* __restrict__ Fin, int nvb,
-                                                     double* __restrict__ mom_out, int node_blocks, int nb) {
+// one closure work item: node block `blk` (< node_blocks) or the wall of instance
+// blk - node_blocks; 64 threads; cl_lds holds the closure LDS (size closure_lds_doubles)
+__device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d, const double* __restrict__ Fin,
+                                              int nvb, double* __restrict__ mom_out, int blk, int node_blocks, int nb,
+                                              double* cl_lds) {
   const int S = sh.S;
   const int lane = threadIdx.x;
-  if ((int)blockIdx.x >= node_blocks) {
+  if (blk >= node_blocks) {
     // wall density: zero net mass flux through x = L/2 (App. A.4); the outgoing fluxes
     // (p_x > 0) use the extrapolated ghosts, the incoming ones are p_x n_w F^eq_w exactly.
-    const int b = blockIdx.x - node_blocks;
+    const int b = blk - node_blocks;
     const InstDev* in = d.inst + b;
     const int V = sh.V;
     const double* F = Fin + (size_t)b * S * V;
@@ -336,7 +339,6 @@ __global__ void __launch_bounds__(64) closure_kernel(Shape sh, DevPtrs d, const 
   }
   // LDS (sizes of this velocity set): moment sums, per-node coefficients, projection
   // tables, per-node g_y and g_z
-  extern __shared__ double cl_lds[];
   const int nphx = sh.Qx * (sh.Nx + 1), nphy = sh.Qy * (sh.Ny + 1), nphz = sh.Qz * (sh.Nz + 1);
   const int oJm = sh.Nx + 1, oay = 2 * (sh.Nx + 1), oaz = oay + sh.Ny + 1, SC = oaz + sh.Nz + 1;
   const int Qyz = sh.Qy + sh.Qz;
@@ -347,7 +349,7 @@ __global__ void __launch_bounds__(64) closure_kernel(Shape sh, DevPtrs d, const 
   double* phiz = phiy + nphy;
   double* gyz = phiz + nphz;
   const int total = sh.B * S;
-  const int g0 = blockIdx.x * nb;
+  const int g0 = blk * nb;
   const int nblk_nodes = min(nb, total - g0);
   for (int e = lane; e < nphx; e += 64) phix[e] = d.phix[e];
   for (int e = lane; e < nphy; e += 64) phiy[e] = d.phiy[e];
@@ -476,6 +478,26 @@ __global__ void __launch_bounds__(64) closure_kernel(Shape sh, DevPtrs d, const 
   }
 }
 
+__global__ void __launch_bounds__(64) closure_kernel(Shape sh, DevPtrs d, const double* __restrict__ Fin, int nvb,
+                                                     double* __restrict__ mom_out, int node_blocks, int nb) {
+  extern __shared__ double cl_lds[];
+  closure_block(sh, d, Fin, nvb, mom_out, blockIdx.x, node_blocks, nb, cl_lds);
+}
+
+// doubles of closure LDS for nb nodes per block
+static inline size_t closure_lds_doubles(const Shape& sh, int nb) {
+  return (size_t)nb * PART_STRIDE + (size_t)nb * (2 * (sh.Nx + 1) + sh.Ny + sh.Nz + 2) + (size_t)sh.Qx * (sh.Nx + 1) +
+         (size_t)sh.Qy * (sh.Ny + 1) + (size_t)sh.Qz * (sh.Nz + 1) + (size_t)nb * (sh.Qy + sh.Qz);
+}
+
+// nodes per closure block: up to 64, fewer when there are few nodes, so the grid keeps
+// several thousand blocks
+static inline int closure_nodes_per_block(int total_nodes) {
+  int nb = CL_NODES;
+  while (nb > 4 && (total_nodes + nb - 1) / nb < 4096) nb >>= 1;
+  return nb;
+}
+
 // ---------------------------------------------------------------------------------------
 // the stage kernel
 
@@ -513,18 +535,15 @@ __device__ __forceinline__ double stencil_flux(bool pos, double px, double w0, d
   return px * interp<SCHEME>(a, b, c, dd, e);
 }
 
+// one tile: instance b, velocity block vb (64 * waves velocities), node chunk ch (cs nodes)
 template <int SCHEME, int STAGE>
-__global__ void __launch_bounds__(256) stage_kernel(Shape sh, DevPtrs d, const double* __restrict__ Fin,
-                                                    const double* Fl, double* Fout, int nvb, int nch, int cs) {
-  extern __shared__ double lds[];
+__device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, const double* __restrict__ Fin,
+                                           const double* Fl, double* Fout, int b, int vb, int ch, int nvb, int nch,
+                                           int cs, double* lds) {
   const int waves = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double* lds_ft = lds;
   double* lds_red = lds + waves * FT_WAVE;
   double* lds_res = lds_red + waves * RED_WAVE;
-  int t = xcd_tile(blockIdx.x, gridDim.x);
-  const int ch = t % nch;
-  t /= nch;
-  const int vb = t % nvb, b = t / nvb;
   const int S = sh.S, V = sh.V, Qx = sh.Qx;
   const int v = vb * blockDim.x + threadIdx.x;
   const bool active = v < V;
@@ -669,6 +688,50 @@ __global__ void __launch_bounds__(256) stage_kernel(Shape sh, DevPtrs d, const d
   }
 }
 
+template <int SCHEME, int STAGE>
+__global__ void __launch_bounds__(256) stage_kernel(Shape sh, DevPtrs d, const double* __restrict__ Fin,
+                                                    const double* Fl, double* Fout, int nvb, int nch, int cs) {
+  extern __shared__ double lds[];
+  int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int ch = t % nch;
+  t /= nch;
+  stage_tile<SCHEME, STAGE>(sh, d, Fin, Fl, Fout, t / nvb, t % nvb, ch, nvb, nch, cs, lds);
+}
+
+// ---------------------------------------------------------------------------------------
+// batched (ragged) launches: one persistent grid serves the tiles of every group
+
+template <int STAGE>
+__global__ void __launch_bounds__(256) batch_stage_kernel(const GroupDesc* __restrict__ groups,
+                                                          const int4* __restrict__ tiles, const int* __restrict__ ntiles) {
+  extern __shared__ double lds[];
+  const int n = *ntiles;
+  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    const int4 tl = tiles[t];
+    const GroupDesc& g = groups[tl.x];
+    const double* Fin = g.d.F[STAGE - 1];
+    double* Fout = g.d.F[STAGE % 3];
+    if (g.sh.scheme == 1)
+      stage_tile<1, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
+    else
+      stage_tile<0, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(64) batch_closure_kernel(const GroupDesc* __restrict__ groups,
+                                                           const int2* __restrict__ items, const int* __restrict__ nitems,
+                                                           int stage) {
+  extern __shared__ double cl_lds[];
+  const int n = *nitems;
+  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    const int2 it = items[t];
+    const GroupDesc& g = groups[it.x];
+    closure_block(g.sh, g.d, g.d.F[stage - 1], g.nvb, nullptr, it.y, g.node_blocks, g.nb, cl_lds);
+    __syncthreads();
+  }
+}
+
 __global__ void __launch_bounds__(256) residual_kernel(Shape sh, DevPtrs d, int nres) {
   const int b = blockIdx.x;
   __shared__ double r0[256], r1[256];
@@ -722,17 +785,11 @@ int launch_partials(const Shape& sh, const DevPtrs& d, const double* F, int cell
 }
 
 int launch_closure(const Shape& sh, const DevPtrs& d, const double* Fin, int nvb, double* mom_out, void* stream) {
-  // nodes per block: up to 64, fewer when there are few nodes, so the grid keeps
-  // several hundred blocks
   const int total = sh.B * sh.S;
-  int nb = CL_NODES;
-  while (nb > 4 && (total + nb - 1) / nb < 4096) nb >>= 1;
+  const int nb = closure_nodes_per_block(total);
   const int node_blocks = (total + nb - 1) / nb;
-  const size_t lds = ((size_t)nb * PART_STRIDE + (size_t)nb * (2 * (sh.Nx + 1) + sh.Ny + sh.Nz + 2) +
-                      (size_t)sh.Qx * (sh.Nx + 1) + (size_t)sh.Qy * (sh.Ny + 1) + (size_t)sh.Qz * (sh.Nz + 1) +
-                      (size_t)nb * (sh.Qy + sh.Qz)) * sizeof(double);
-  hipLaunchKernelGGL(closure_kernel, dim3(node_blocks + sh.B), dim3(64), lds, (hipStream_t)stream, sh, d, Fin, nvb,
-                     mom_out, node_blocks, nb);
+  hipLaunchKernelGGL(closure_kernel, dim3(node_blocks + sh.B), dim3(64), closure_lds_doubles(sh, nb) * sizeof(double),
+                     (hipStream_t)stream, sh, d, Fin, nvb, mom_out, node_blocks, nb);
   return (int)hipGetLastError();
 }
 
@@ -760,6 +817,32 @@ int launch_stage(const Shape& sh, const DevPtrs& d, int stage, const double* Fin
 
 int launch_residual(const Shape& sh, const DevPtrs& d, int nres, void* stream) {
   hipLaunchKernelGGL(residual_kernel, dim3(sh.B), dim3(256), 0, (hipStream_t)stream, sh, d, nres);
+  return (int)hipGetLastError();
+}
+
+size_t stage_lds_bytes_for(int waves) { return stage_lds_bytes(waves); }
+size_t closure_lds_bytes_for(const Shape& sh, int nb) { return closure_lds_doubles(sh, nb) * sizeof(double); }
+int closure_nodes_for(int total_nodes) { return closure_nodes_per_block(total_nodes); }
+
+int launch_batch_stage(int stage, const GroupDesc* groups, const void* tiles, const int* ntiles, int grid, int waves,
+                       size_t lds_bytes, void* stream) {
+  const int4* t = (const int4*)tiles;
+  if (stage == 1)
+    hipLaunchKernelGGL(batch_stage_kernel<1>, dim3(grid), dim3(64 * waves), lds_bytes, (hipStream_t)stream, groups, t,
+                       ntiles);
+  else if (stage == 2)
+    hipLaunchKernelGGL(batch_stage_kernel<2>, dim3(grid), dim3(64 * waves), lds_bytes, (hipStream_t)stream, groups, t,
+                       ntiles);
+  else
+    hipLaunchKernelGGL(batch_stage_kernel<3>, dim3(grid), dim3(64 * waves), lds_bytes, (hipStream_t)stream, groups, t,
+                       ntiles);
+  return (int)hipGetLastError();
+}
+
+int launch_batch_closure(int stage, const GroupDesc* groups, const void* items, const int* nitems, int grid,
+                         size_t lds_bytes, void* stream) {
+  hipLaunchKernelGGL(batch_closure_kernel, dim3(grid), dim3(64), lds_bytes, (hipStream_t)stream, groups,
+                     (const int2*)items, nitems, stage);
   return (int)hipGetLastError();
 }
 

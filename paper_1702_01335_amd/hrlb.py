@@ -23,7 +23,8 @@ MOMENT_NAMES = ('n', 'ux', 'uy', 'uz', 'T', 'Pxx', 'Pyy', 'Pzz', 'Pxy', 'Pxz', '
 EXPORTS = ('hrlb_last_error', 'hrlb_init_quadrature', 'hrlb_quad_free', 'hrlb_quad_size', 'hrlb_quad_nodes',
            'hrlb_state_bytes', 'hrlb_init_state', 'hrlb_sim_free', 'hrlb_step', 'hrlb_moments', 'hrlb_residual',
            'hrlb_get_state', 'hrlb_set_state', 'hrlb_set_launch', 'hrlb_get_launch', 'hrlb_autotune', 'hrlb_set_graph',
-           'hrlb_set_timing', 'hrlb_get_timing')
+           'hrlb_set_timing', 'hrlb_get_timing', 'hrlb_batch_bytes', 'hrlb_batch_create', 'hrlb_batch_step',
+           'hrlb_batch_residual', 'hrlb_batch_set_active', 'hrlb_batch_info', 'hrlb_batch_free')
 
 
 class HrlbError(RuntimeError):
@@ -81,8 +82,17 @@ def load():
     lib.hrlb_set_graph.argtypes = [vp, ctypes.c_int]
     lib.hrlb_set_timing.argtypes = [vp, ctypes.c_int]
     lib.hrlb_get_timing.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
+    lib.hrlb_batch_bytes.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz)]
+    lib.hrlb_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, sz, vp,
+                                      ctypes.POINTER(vp)]
+    lib.hrlb_batch_step.argtypes = [vp, ctypes.c_int]
+    lib.hrlb_batch_residual.argtypes = [vp, dp]
+    lib.hrlb_batch_set_active.argtypes = [vp, ip]
+    lib.hrlb_batch_info.argtypes = [vp, ip, ip, ip, ip]
+    lib.hrlb_batch_free.argtypes = [vp]
+    lib.hrlb_batch_free.restype = None
     for name in EXPORTS:
-        if name not in ('hrlb_last_error', 'hrlb_quad_free', 'hrlb_sim_free'):
+        if name not in ('hrlb_last_error', 'hrlb_quad_free', 'hrlb_sim_free', 'hrlb_batch_free'):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -245,4 +255,57 @@ class Solver:
             except Exception:
                 pass
             _lib.hrlb_sim_free(self.handle)
+            self.handle = None
+
+
+class Batch:
+    """Several Solvers (groups of instances that differ in velocity set, node count or
+    scheme) advanced together by one persistent launch per kernel per stage, graph-captured.
+    All solvers must use the torch stream current at construction."""
+
+    def __init__(self, solvers, cells, waves):
+        import torch
+        self.torch = torch
+        self.solvers = list(solvers)
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s.handle for s in self.solvers])
+        self._arr = arr
+        nbytes = ctypes.c_size_t()
+        _check(load().hrlb_batch_bytes(arr, len(arr), cells, waves, ctypes.byref(nbytes)))
+        dev = self.solvers[0].device
+        self.work = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        _check(load().hrlb_batch_create(arr, len(arr), cells, waves, ctypes.c_void_p(self.work.data_ptr()),
+                                        self.work.numel(), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+        self.B = sum(s.B for s in self.solvers)
+
+    def step(self, nsteps=1):
+        _check(load().hrlb_batch_step(self.handle, nsteps))
+
+    def residual(self, raise_on_fault=True):
+        out = np.zeros(self.B)
+        rc = load().hrlb_batch_residual(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        if raise_on_fault:
+            _check(rc)
+            return out
+        return rc, out
+
+    def set_active(self, active):
+        a = np.ascontiguousarray(np.asarray(active, dtype=np.int32))
+        assert a.shape == (self.B,)
+        _check(load().hrlb_batch_set_active(self.handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+
+    def info(self):
+        v = [ctypes.c_int() for _ in range(4)]
+        _check(load().hrlb_batch_info(self.handle, *[ctypes.byref(x) for x in v]))
+        return dict(zip(('tiles', 'closure_items', 'grid_stage', 'grid_closure'), [x.value for x in v]))
+
+    def __del__(self):
+        if getattr(self, 'handle', None) and _lib is not None:
+            try:
+                self.stream.synchronize()
+            except Exception:
+                pass
+            _lib.hrlb_batch_free(self.handle)
             self.handle = None
