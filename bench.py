@@ -40,6 +40,9 @@ def parse():
     ap.add_argument('--copy-probe-mib', type=int, default=0,
                     help='also run one device copy of this size (calibrates HBM byte counters under a profiler)')
     ap.add_argument('--cpu-seconds', type=float, default=15.0)
+    ap.add_argument('--no-sweep', action='store_true', help='skip the ragged-sweep measurements')
+    ap.add_argument('--sweep-instances', type=int, default=256)
+    ap.add_argument('--steady-instances', type=int, default=16)
     return ap.parse_args()
 
 
@@ -89,6 +92,73 @@ def profiled_traffic(tag, bytes_per_launch):
     ks = tr['stage_kernels'].values()
     t = sum(k['fetch_bytes'] + k['write_bytes'] for k in ks) / len(ks)
     return {'bytes_per_launch': t, 'over_algorithmic': t / bytes_per_launch, 'source': f'profiles/{tag}.md'}
+
+
+def sweep_section(n_inst, n_steady, steps):
+    """Ragged sweep measurements.  Throughput: n_inst instances drawn from the sweep
+    distribution (kn log-uniform in [0.01, 100], u_w in [0.05, 0.6], omega in
+    {0.5, 0.72, 0.81, 1}, Qx in {4, 8, 16, 32}, S in {64, 128, 256}, Qy = Qz = 5, upwind2)
+    advanced as one autotuned persistent batch, against the same groups stepped one after
+    another and against every instance stepped alone.  Time to steady state: n_steady
+    instances of the same distribution restricted to S = 64 and Qx in {4, 8}, run to
+    residual 1e-10 as one batch that retires converged instances, against the same
+    instances run one at a time."""
+    import numpy as np
+    import torch
+    from paper_1702_01335_amd import hrlb
+    from paper_1702_01335_amd.sweep import Sweep, sample
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, k):
+        fn(2)
+        torch.cuda.synchronize()
+        e0.record()
+        fn(k)
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    sw = Sweep(sample(n_inst, 20170204))
+    cells, waves, _ = sw.autotune(probe_steps=5)
+    pairs = sw.pairs()
+    ms_b = timed(sw.batch.step, steps)
+    ms_g = 0.0
+    for _, _, s in sw.groups:
+        s.autotune(probe_steps=3)
+        s.set_graph(True)
+        ms_g += timed(s.step, max(5, steps // 4))
+    del sw
+    torch.cuda.empty_cache()
+    ms_i = 0.0
+    sw1 = Sweep(sample(n_inst, 20170204), cells=4)
+    for i in sw1.order:
+        d = sw1.instances[i]
+        s = sw1._solver((d['Qx'], d['S']), [i])
+        s.set_graph(True)
+        ms_i += timed(s.step, 5)
+        del s
+    del sw1
+    torch.cuda.empty_cache()
+    out = dict(instances=n_inst, pairs=pairs, launch=dict(cells=cells, waves=waves, graph=True),
+               batched_ms_per_step=ms_b, value=pairs / ms_b / 1e6, unit='G pair-updates/s',
+               groups_one_by_one_ms_per_step=ms_g, instances_one_by_one_ms_per_step=ms_i,
+               speedup_vs_groups=ms_g / ms_b, speedup_vs_instances=ms_i / ms_b)
+    if n_steady:
+        tol, budget, every = 1e-10, 400000, 1000
+        inst = sample(n_steady, 20170206, qx=(4, 8), nodes=(64,))
+        sw = Sweep(inst)
+        c, w, _ = sw.autotune(probe_steps=5)
+        st_b, R_b, wall_b = sw.run_to_steady(tol, budget, every)
+        st_p, R_p, wall_p = sw.run_plain(tol, budget, every)
+        out['steady'] = dict(instances=n_steady, tol=tol, check_every=every,
+                             subset='kn log-uniform [0.01, 100], u_w [0.05, 0.6], omega sampled, Qx in {4, 8}, S = 64',
+                             launch=dict(cells=c, waves=w),
+                             batched_wall_s=wall_b, plain_wall_s=wall_p, speedup=wall_p / wall_b,
+                             converged_batched=int((st_b > 0).sum()), converged_plain=int((st_p > 0).sum()),
+                             steps_max=int(st_b.max()), steps_median=float(np.median(st_b)),
+                             steps_equal=bool(np.array_equal(st_b, st_p)),
+                             max_residual=float(max(R_b.max(), R_p.max())))
+    return out
 
 
 def cpu_baseline(wl, seconds):
@@ -189,6 +259,10 @@ def main():
         'residual_max': float(res.max()),
         'wall_s_timed': wall,
     }
+    if not args.no_sweep:
+        del solver
+        torch.cuda.empty_cache()
+        out['sweep'] = sweep_section(args.sweep_instances, args.steady_instances, min(args.steps, 50))
     if not args.no_cpu:
         out['cpu_baseline'] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

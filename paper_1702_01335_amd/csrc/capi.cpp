@@ -755,6 +755,14 @@ int hrlb_batch_step(hrlb_batch* bt, int nsteps) {
     if (g) (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e, "batch_step: graph capture");
   }
+  // a sim stepped on its own or by another batch since may hold moment partials laid out
+  // for another wave count: re-lay them from the current state first
+  for (hrlb_sim* sm : bt->sims) {
+    const int nvb = (sm->sh.V + 64 * bt->waves - 1) / (64 * bt->waves);
+    if (sm->part_nvb != nvb)
+      HIP_TRY((hipError_t)launch_partials(sm->sh, sm->d, sm->d.F[0], bt->cells, bt->waves, bt->stream),
+              "batch_step: partials");
+  }
   for (int n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(bt->gexec, bt->stream), "batch_step: graph launch");
   for (hrlb_sim* sm : bt->sims) {
     const int nvb = (sm->sh.V + 64 * bt->waves - 1) / (64 * bt->waves), nch = (sm->sh.S + bt->cells - 1) / bt->cells;

@@ -98,3 +98,56 @@ def test_sweep_runs_to_steady_with_retirement():
     print(f"[sweep] steps {steps.tolist()} wall {wall:.2f}s", flush=True)
     assert (steps > 0).all()
     assert (R < 1e-8).all()
+
+
+def test_batches_sharing_sims_relayout_partials():
+    """Two batches with different wave counts over the same sims, interleaved with a step of
+    one sim alone: every switch re-lays the moment partials, so the result matches one
+    uninterrupted run up to reduction order."""
+    sims = [make_solver(wl, nb, 100 * g)[0] for g, (wl, nb) in enumerate(zip(GROUPS, BATCH))]
+    a = hrlb.Batch(sims, CELLS, 1)
+    b = hrlb.Batch(sims, 2, 3)
+    a.step(2)
+    b.step(2)
+    sims[1].step(1)
+    a.step(1)
+    ref = [make_solver(wl, nb, 100 * g)[0] for g, (wl, nb) in enumerate(zip(GROUPS, BATCH))]
+    r = hrlb.Batch(ref, CELLS, 1)
+    r.step(5)
+    sims[1].synchronize()
+    for g, (s, t) in enumerate(zip(sims, ref)):
+        F, Fr = s.get_state().cpu().numpy(), t.get_state().cpu().numpy()
+        if g == 1:
+            t.step(1)
+            Fr = t.get_state().cpu().numpy()
+        err = np.abs(F - Fr).max() / np.abs(Fr).max()
+        print(f"[relayout] group {g}: max rel diff {err:.2e}", flush=True)
+        assert err <= 1e-13
+
+
+def test_sweep_autotune_restores_state():
+    inst = sample(6, 11, kn_range=(0.3, 3.0), qx=(4, 8), nodes=(12, 16))
+    sw = Sweep(inst, Qy=3, Qz=3, cells=4, waves=1)
+    sw.batch.step(3)
+    before = [g[2].get_state().cpu().numpy() for g in sw.groups]
+    c, w, ms = sw.autotune(cells=(2, 8), waves=(1, 2), probe_steps=2)
+    assert (c, w) in {(2, 1), (2, 2), (8, 1), (8, 2)} and ms > 0
+    after = [g[2].get_state().cpu().numpy() for g in sw.groups]
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    sw.batch.step(2)
+    ref = Sweep(inst, Qy=3, Qz=3, cells=c, waves=w)
+    ref.batch.step(5)
+    for g, h in zip(sw.groups, ref.groups):
+        F, Fr = g[2].get_state().cpu().numpy(), h[2].get_state().cpu().numpy()
+        assert np.abs(F - Fr).max() / np.abs(Fr).max() <= 1e-13
+
+
+def test_sweep_plain_matches_batched_steps():
+    inst = sample(5, 20170207, kn_range=(0.3, 3.0), qx=(4,), nodes=(12, 16))
+    sw = Sweep(inst, Qy=4, Qz=4, scheme='upwind2', cells=4, waves=2)
+    st_b, R_b, _ = sw.run_to_steady(tol=1e-8, max_steps=60000, check_every=500)
+    st_p, R_p, wall = sw.run_plain(tol=1e-8, max_steps=60000, check_every=500)
+    print(f"[plain] batched {st_b.tolist()} plain {st_p.tolist()} wall {wall:.2f}s", flush=True)
+    assert (st_b > 0).all() and (st_p > 0).all()
+    assert np.abs(st_b - st_p).max() <= 500
