@@ -18,6 +18,10 @@ solver       moments (Eq. qdef), relaxation-time laws (Secs. IV-VI), grid (App. 
              WENO-5 / 2nd-order upwind fluxes (App. A.3), boundary ghosts (App. A.4),
              TVD RK3 (App. A.1), residual.
 diagnostics  Sec. IV / VI observables (u_slip, u'(0), mass flow, mean T_xy, nu, Pi, T_0).
+warmstart    seed populations from predicted profiles: discrete equilibrium times the
+             stress and heat-flux (Shakhov-form, Eq. sdef) correction polynomial.
+mlp          the warm-start network: forward, MSE loss, chain-rule gradient with the
+             bfloat16 rounding points of the GPU kernels, AdamW.
 
 Parity status of each function is given in its docstring; functions without an
 independent pin say "parity unpinned".
