@@ -149,6 +149,22 @@ int hrlb_get_state(hrlb_sim* sim, double* d_out);
 int hrlb_set_state(hrlb_sim* sim, const double* d_in);
 
 /*
+ * seed_state -- warm start: overwrite the state with populations built from a moment
+ * table d_table[batch][S][14] (device, caller-owned, the column order of hrlb_moments).
+ * Each node gets the projected discrete equilibrium at its n, u, T (Sec. III) times
+ * 1 + Pi_ab xi_a xi_b / (2 n T^2) + (xi^2 / (5T) - 1) xi.q / (n T^2), with xi = p - u and
+ * Pi = P - n T I: the heat-flux polynomial is that of the Shakhov factor (Eq. sdef) with
+ * 1 - Pr replaced by 1, and the stress term carries the pressure deviator.  With
+ * equilibrium orders >= 6 on every axis the seed has exactly the table's moments.
+ * Fallback: an instance whose table has a non-finite entry, n <= 0 or T <= 0 at any node
+ * is seeded with the equilibrium at rest (n0, u = 0, T_w) as hrlb_init_state does;
+ * h_fallback[batch] (host, may be NULL) receives 1 for those instances.  Recomputes the
+ * moment partials, clears the numeric-fault flags and synchronises the stream.
+ * Errors: HRLB_EINVAL (NULL sim or table), HRLB_EHIP.
+ */
+int hrlb_seed_state(hrlb_sim* sim, const double* d_table, int* h_fallback);
+
+/*
  * Launch shape of the stage kernel: `cells` nodes marched per thread (1..4096; 0 = the
  * library's default) and `waves` 64-lane waves per workgroup along v (1..4; 0 = default).
  * Any shape gives the same result up to the summation order of the moment partials.

@@ -3,8 +3,9 @@
     python -m paper_1702_01335_amd.build
 
 Host C++ (quadrature tables, C ABI) is compiled by g++ against the HIP headers, the
-kernels by hipcc for gfx950 with packed-FP32 instruction selection disabled, and the
-objects are linked by hipcc into paper_1702_01335_amd/libhrlb.so.
+kernels (solver and warm-start network, with its C ABI) by hipcc for gfx950 with
+packed-FP32 instruction selection disabled, and the objects are linked by hipcc into
+paper_1702_01335_amd/libhrlb.so.
 """
 import os
 import subprocess
@@ -36,10 +37,11 @@ def build(verbose=False):
         _run(['g++', '-O2', '-std=c++17', '-fPIC', '-Wall', '-D__HIP_PLATFORM_AMD__', '-I', os.path.join(ROCM, 'include')]
              + INC + ['-c', os.path.join(CSRC, src), '-o', obj], verbose)
         objs.append(obj)
-    kobj = os.path.join(BUILD, 'kernels.o')
-    _run([HIPCC, '-O3', '-std=c++17', '-fPIC'] + HIP_DEVICE_FLAGS + INC + ['-c', os.path.join(CSRC, 'kernels.hip'), '-o', kobj],
-         verbose)
-    objs.append(kobj)
+    for src in ('kernels.hip', 'mlp.hip'):
+        kobj = os.path.join(BUILD, src.replace('.hip', '.o'))
+        _run([HIPCC, '-O3', '-std=c++17', '-fPIC'] + HIP_DEVICE_FLAGS + INC + ['-c', os.path.join(CSRC, src), '-o', kobj],
+             verbose)
+        objs.append(kobj)
     tmp = LIB + '.tmp'
     _run([HIPCC, '-shared', '-fPIC', '--offload-arch=gfx950'] + objs + ['-o', tmp], verbose)
     os.replace(tmp, LIB)

@@ -41,6 +41,10 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
+namespace hrlb {
+int set_error(int code, const char* msg) { return fail(code, msg); }
+}  // namespace hrlb
+
 struct hrlb_quad {
   QuadTables t;
 };
@@ -861,6 +865,22 @@ int hrlb_set_state(hrlb_sim* s, const double* d_in) {
   HIP_TRY(hipMemcpyAsync(s->d.F[0], d_in, bytes, hipMemcpyDeviceToDevice, s->stream), "set_state: copy");
   hipError_t e = (hipError_t)launch_partials(s->sh, s->d, s->d.F[0], s->cells, s->waves, s->stream);
   if (e != hipSuccess) return hip_fail(e, "set_state: launch");
+  s->part_nvb = (s->sh.V + 64 * s->waves - 1) / (64 * s->waves);
+  s->resid_nres = 0;
+  return HRLB_OK;
+}
+
+int hrlb_seed_state(hrlb_sim* s, const double* d_table, int* h_fallback) {
+  if (!s || !d_table) return fail(HRLB_EINVAL, "seed_state: NULL argument");
+  hipError_t e = (hipError_t)launch_seed(s->sh, s->d, d_table, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "seed_state: launch");
+  if (h_fallback)
+    HIP_TRY(hipMemcpyAsync(h_fallback, s->d.flags, s->sh.B * sizeof(int), hipMemcpyDeviceToHost, s->stream),
+            "seed_state: copy");
+  e = (hipError_t)launch_clear_flags(s->sh, s->d, s->stream);
+  if (e == hipSuccess) e = (hipError_t)launch_partials(s->sh, s->d, s->d.F[0], s->cells, s->waves, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "seed_state: launch");
+  HIP_TRY(hipStreamSynchronize(s->stream), "seed_state: synchronize");
   s->part_nvb = (s->sh.V + 64 * s->waves - 1) / (64 * s->waves);
   s->resid_nres = 0;
   return HRLB_OK;

@@ -95,8 +95,13 @@ struct WorkLayout {
 WorkLayout work_layout(const Shape& sh);
 
 // Kernel launchers (kernels.hip).  Every launcher returns a hipError_t cast to int.
+// record the message returned by hrlb_last_error() for this thread; returns code
+int set_error(int code, const char* msg);
+
 int launch_setup_tables(const Shape& sh, const DevPtrs& d, void* stream);
 int launch_init_state(const Shape& sh, const DevPtrs& d, const double* perturb, double eps, void* stream);
+int launch_seed(const Shape& sh, const DevPtrs& d, const double* tab, void* stream);
+int launch_clear_flags(const Shape& sh, const DevPtrs& d, void* stream);
 int launch_partials(const Shape& sh, const DevPtrs& d, const double* F, int cells, int waves, void* stream);
 int launch_closure(const Shape& sh, const DevPtrs& d, const double* Fin, int nvb, double* mom_out, void* stream);
 int launch_stage(const Shape& sh, const DevPtrs& d, int stage, const double* Fin, const double* Fl, double* Fout,

@@ -212,6 +212,71 @@ __global__ void init_state_kernel(Shape sh, DevPtrs d, const double* __restrict_
 }
 
 // ---------------------------------------------------------------------------------------
+// warm-start seed from a moment table (per node: n, ux, uy, uz, T, Pxx, Pyy, Pzz, Pxy, Pxz,
+// Pyz, qx, qy, qz):  F = F^eq(n, u, T) (1 + Pi_ab xi_a xi_b / (2 n T^2)
+//                                     + (xi^2 / (5T) - 1) xi.q / (n T^2)),
+// Pi_ab = P_ab - n T delta_ab, xi = p - u.  F^eq is the projected discrete equilibrium
+// (Sec. III) and the heat-flux polynomial is that of the Shakhov factor (Eq. sdef) with
+// 1 - Pr replaced by 1.  An instance with a node that is not finite or has n <= 0 or
+// T <= 0 is seeded with the equilibrium at rest instead (flags[b] = 1).
+
+constexpr int TAB = 14;
+
+__global__ void __launch_bounds__(256) seed_check_kernel(Shape sh, DevPtrs d, const double* __restrict__ tab) {
+  const int b = blockIdx.x;
+  int bad = 0;
+  for (int idx = threadIdx.x; idx < sh.S * TAB; idx += blockDim.x) {
+    const double x = tab[(size_t)b * sh.S * TAB + idx];
+    const int c = idx % TAB;
+    if (!isfinite(x) || ((c == 0 || c == 4) && !(x > 0.0))) bad = 1;
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) d.flags[b] = bad;
+}
+
+__global__ void __launch_bounds__(256) seed_kernel(Shape sh, DevPtrs d, const double* __restrict__ tab) {
+  const int node = blockIdx.x, b = node / sh.S;
+  double* F = d.F[0] + (size_t)node * sh.V;
+  if (d.flags[b]) {
+    const double n0 = d.inst[b].n0;
+    for (int v = threadIdx.x; v < sh.V; v += blockDim.x) F[v] = n0 * d.g_rest[(size_t)b * sh.V + v];
+    return;
+  }
+  __shared__ double gx[2 * QX_MAX], gy[QYZ_MAX], gz[QYZ_MAX];
+  const double* t = tab + (size_t)node * TAB;
+  const double n = t[0], ux = t[1], uy = t[2], uz = t[3], T = t[4];
+  {
+    double I[NX_MAX + 1], Jp[NX_MAX + 1], Jm[NX_MAX + 1], ay[NYZ_MAX + 1], az[NYZ_MAX + 1];
+    half_gauss_moments(ux, T, I);
+    half_projection(d.cx, sh.Nx, I, Jp);
+    half_gauss_moments(-ux, T, I);
+    half_projection(d.cx, sh.Nx, I, Jm);
+    full_coeffs(uy, T, ay);
+    full_coeffs(uz, T, az);
+    for (int i = threadIdx.x; i < 2 * sh.Qx; i += blockDim.x) gx[i] = n * gx_node(d.phix, sh.Qx, sh.Nx, i, Jp, Jm);
+    for (int j = threadIdx.x; j < sh.Qy; j += blockDim.x) gy[j] = full_node(d.phiy, sh.Ny, j, ay);
+    for (int k = threadIdx.x; k < sh.Qz; k += blockDim.x) gz[k] = full_node(d.phiz, sh.Nz, k, az);
+  }
+  __syncthreads();
+  const double nT = n * T, c2 = 0.5 / (nT * T), c3 = 1.0 / (nT * T), c5 = 1.0 / (5.0 * T);
+  const double sxx = (t[5] - nT) * c2, syy = (t[6] - nT) * c2, szz = (t[7] - nT) * c2;
+  const double sxy = 2.0 * t[8] * c2, sxz = 2.0 * t[9] * c2, syz = 2.0 * t[10] * c2;
+  const double hx = t[11] * c3, hy = t[12] * c3, hz = t[13] * c3;
+  for (int v = threadIdx.x; v < sh.V; v += blockDim.x) {
+    const int i = v / sh.QyQz, jk = v - i * sh.QyQz, j = jk / sh.Qz, k = jk - j * sh.Qz;
+    const double x = d.px[i] - ux, y = d.py[j] - uy, z = d.pz[k] - uz;
+    const double stress = sxx * x * x + syy * y * y + szz * z * z + sxy * x * y + sxz * x * z + syz * y * z;
+    const double heat = ((x * x + y * y + z * z) * c5 - 1.0) * (hx * x + hy * y + hz * z);
+    F[v] = gx[i] * gy[j] * gz[k] * (1.0 + stress + heat);
+  }
+}
+
+__global__ void clear_flags_kernel(int* flags, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = 0;
+}
+
+// ---------------------------------------------------------------------------------------
 // moment partials on the matrix cores
 //
 // The 13 moment sums of a node over a wave's 64 velocities are a dense contraction over
@@ -771,6 +836,18 @@ int launch_init_state(const Shape& sh, const DevPtrs& d, const double* perturb, 
   const size_t total = (size_t)sh.B * sh.S * sh.V;
   const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
   hipLaunchKernelGGL(init_state_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, sh, d, perturb, eps);
+  return (int)hipGetLastError();
+}
+
+int launch_seed(const Shape& sh, const DevPtrs& d, const double* tab, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(seed_check_kernel, dim3(sh.B), dim3(256), 0, st, sh, d, tab);
+  hipLaunchKernelGGL(seed_kernel, dim3(sh.B * sh.S), dim3(256), 0, st, sh, d, tab);
+  return (int)hipGetLastError();
+}
+
+int launch_clear_flags(const Shape& sh, const DevPtrs& d, void* stream) {
+  hipLaunchKernelGGL(clear_flags_kernel, dim3((sh.B + 255) / 256), dim3(256), 0, (hipStream_t)stream, d.flags, sh.B);
   return (int)hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ EXPORTS = ('hrlb_last_error', 'hrlb_init_quadrature', 'hrlb_quad_free', 'hrlb_qu
            'hrlb_state_bytes', 'hrlb_init_state', 'hrlb_sim_free', 'hrlb_step', 'hrlb_moments', 'hrlb_residual',
            'hrlb_get_state', 'hrlb_set_state', 'hrlb_set_launch', 'hrlb_get_launch', 'hrlb_autotune', 'hrlb_set_graph',
            'hrlb_set_timing', 'hrlb_get_timing', 'hrlb_batch_bytes', 'hrlb_batch_create', 'hrlb_batch_step',
-           'hrlb_batch_residual', 'hrlb_batch_set_active', 'hrlb_batch_info', 'hrlb_batch_free')
+           'hrlb_batch_residual', 'hrlb_batch_set_active', 'hrlb_batch_info', 'hrlb_batch_free', 'hrlb_seed_state')
 
 
 class HrlbError(RuntimeError):
@@ -76,6 +76,7 @@ def load():
     lib.hrlb_residual.argtypes = [vp, dp]
     lib.hrlb_get_state.argtypes = [vp, vp]
     lib.hrlb_set_state.argtypes = [vp, vp]
+    lib.hrlb_seed_state.argtypes = [vp, vp, ip]
     lib.hrlb_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.hrlb_get_launch.argtypes = [vp, ip, ip]
     lib.hrlb_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ip, ip, dp]
@@ -218,6 +219,17 @@ class Solver:
         assert tuple(F.shape) == (self.B, self.S, self.V)
         self._staged = F
         _check(load().hrlb_set_state(self.handle, ctypes.c_void_p(F.data_ptr())))
+
+    def seed_state(self, table):
+        """Warm start from a moment table (torch float64 [B, S, 14] on the device, the
+        column order of moments()).  Returns the per-instance fallback flags (1 where the
+        table was invalid and the equilibrium at rest was used)."""
+        t = table.to(device=self.device, dtype=self.torch.float64).contiguous()
+        assert tuple(t.shape) == (self.B, self.S, 14)
+        fb = np.zeros(self.B, dtype=np.int32)
+        _check(load().hrlb_seed_state(self.handle, ctypes.c_void_p(t.data_ptr()),
+                                      fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+        return fb
 
     def set_launch(self, cells, waves):
         _check(load().hrlb_set_launch(self.handle, cells, waves))

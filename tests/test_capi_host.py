@@ -1,5 +1,5 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads, exports every symbol
-include/hrlb.h declares, builds velocity sets that match the oracle's independently
+include/hrlb.h and include/hrlb_mlp.h declare, builds velocity sets that match the oracle's independently
 constructed Gauss rules, and rejects invalid arguments before touching device memory."""
 import ctypes
 import os
@@ -9,13 +9,13 @@ import numpy as np
 import pytest
 
 from oracle import quadrature as oq
-from paper_1702_01335_amd import hrlb
+from paper_1702_01335_amd import hrlb, network
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_symbols():
-    src = open(os.path.join(ROOT, 'include', 'hrlb.h')).read()
+    src = ''.join(open(os.path.join(ROOT, 'include', h)).read() for h in sorted(os.listdir(os.path.join(ROOT, 'include'))))
     return sorted(set(re.findall(r'\b(hrlb_[a-z_]+)\s*\(', src)))
 
 
@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 15
     for name in names:
         assert hasattr(lib, name), name
-    assert set(names) == set(hrlb.EXPORTS)
+    assert set(names) == set(hrlb.EXPORTS) | set(network.EXPORTS)
 
 
 @pytest.mark.parametrize("Qx", [1, 2, 4, 7, 16, 32, 50, 100, 128])
@@ -112,3 +112,35 @@ def test_init_state_rejects_small_buffers_and_bad_shapes():
     with pytest.raises(hrlb.HrlbError) as e:   # misaligned
         hrlb.init_state(q.handle, 8, 0, [p], FakeBuf((1 << 20) + 8, sb), FakeBuf(1 << 30, wb), 0)
     assert e.value.code == hrlb.HRLB_EINVAL
+
+
+def test_mlp_sizes_and_argument_checks():
+    lib = network.load()
+    sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.hrlb_mlp_bytes(0, ctypes.byref(sb), ctypes.byref(wb)) == hrlb.HRLB_EINVAL
+    assert lib.hrlb_mlp_bytes((1 << 22) + 1, ctypes.byref(sb), ctypes.byref(wb)) == hrlb.HRLB_EINVAL
+    assert lib.hrlb_mlp_bytes(64, ctypes.byref(sb), ctypes.byref(wb)) == hrlb.HRLB_OK
+    s64, w64 = sb.value, wb.value
+    assert lib.hrlb_mlp_bytes(4096, ctypes.byref(sb), ctypes.byref(wb)) == hrlb.HRLB_OK
+    assert sb.value == s64 and wb.value > w64
+    # weights, two AdamW moments (fp32) and the bf16 copy of the padded parameter array
+    assert s64 >= network.NPARAMS * (3 * 4 + 2)
+    # the checks below fail before any device memory is touched (the pointers are never used)
+    fake = ctypes.c_void_p(1 << 20)
+    h = ctypes.c_void_p()
+    bad = network.norm_vector(np.zeros(5), np.ones(5), np.zeros(8), np.r_[np.ones(7), 0.0])
+    good = network.norm_vector(np.zeros(5), np.ones(5), np.zeros(8), np.ones(8))
+    fp = ctypes.POINTER(ctypes.c_float)
+    assert lib.hrlb_mlp_create(fake, s64, fake, w64, 64, None, 0, bad.ctypes.data_as(fp), None, ctypes.byref(h)) \
+        == hrlb.HRLB_EINVAL
+    assert b'std' in lib.hrlb_last_error()
+    assert lib.hrlb_mlp_create(fake, s64 - 1, fake, w64, 64, None, 0, good.ctypes.data_as(fp), None,
+                               ctypes.byref(h)) == hrlb.HRLB_ENOMEM
+    assert lib.hrlb_mlp_create(ctypes.c_void_p((1 << 20) + 8), s64, fake, w64, 64, None, 0, good.ctypes.data_as(fp),
+                               None, ctypes.byref(h)) == hrlb.HRLB_EINVAL
+    assert lib.hrlb_mlp_create(None, s64, fake, w64, 64, None, 0, good.ctypes.data_as(fp), None,
+                               ctypes.byref(h)) == hrlb.HRLB_EINVAL
+    assert not h.value
+    assert lib.hrlb_mlp_forward(None, fake, 4, fake) == hrlb.HRLB_EINVAL
+    assert lib.hrlb_mlp_train_step(None, fake, fake, None, 4, 1e-3, 0.0, None) == hrlb.HRLB_EINVAL
+    assert lib.hrlb_seed_state(None, fake, None) == hrlb.HRLB_EINVAL
