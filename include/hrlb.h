@@ -156,13 +156,16 @@ int hrlb_set_state(hrlb_sim* sim, const double* d_in);
  * Pi = P - n T I: the heat-flux polynomial is that of the Shakhov factor (Eq. sdef) with
  * 1 - Pr replaced by 1, and the stress term carries the pressure deviator.  With
  * equilibrium orders >= 6 on every axis the seed has exactly the table's moments.
+ * preserve_mass != 0 scales each instance's seed by one factor so that its mass
+ * sum_s n_s dx_s equals that of the equilibrium start, n0 times the half-channel length:
+ * the scheme conserves mass (App. A.4), so the steady state reached depends on it.
  * Fallback: an instance whose table has a non-finite entry, n <= 0 or T <= 0 at any node
  * is seeded with the equilibrium at rest (n0, u = 0, T_w) as hrlb_init_state does;
  * h_fallback[batch] (host, may be NULL) receives 1 for those instances.  Recomputes the
  * moment partials, clears the numeric-fault flags and synchronises the stream.
  * Errors: HRLB_EINVAL (NULL sim or table), HRLB_EHIP.
  */
-int hrlb_seed_state(hrlb_sim* sim, const double* d_table, int* h_fallback);
+int hrlb_seed_state(hrlb_sim* sim, const double* d_table, int preserve_mass, int* h_fallback);
 
 /*
  * Launch shape of the stage kernel: `cells` nodes marched per thread (1..4096; 0 = the

@@ -25,7 +25,8 @@ which fixes P_zz = 3 n T - P_xx - P_yy.
 Pins (tests/test_oracle_warmstart.py): with N >= 6 on every axis the moments of the seed
 equal the profiles it was built from (n, u, T, P, q) to rounding; with Pi = 0 and q = 0 the
 seed is the discrete equilibrium; the heat-flux term with q scaled by (1 - Pr) equals the
-Shakhov target of the solver oracle.
+Shakhov target of the solver oracle; the mass-preserving scaling gives the seed the mass
+of the equilibrium start and leaves u and T unchanged.
 """
 import numpy as np
 
@@ -68,6 +69,19 @@ def seed(table, vs):
     qxi = q[0][..., None] * xi['x'] + q[1][..., None] * xi['y'] + q[2][..., None] * xi['z']
     heat = (xi2 / (5.0 * T[..., None]) - 1.0) * qxi
     return feq * (1.0 + stress / (2.0 * denom) + heat / denom)
+
+
+def mass_preserving(table, dx, n0):
+    """The table scaled by the one factor c = n0 sum_s dx_s / sum_s n_s dx_s that gives the
+    seed the mass of the equilibrium start (extensive columns n, P, q times c; u and T
+    unchanged), for table (S, 14) and node widths dx (S,).  The scheme conserves mass
+    (bounce-back centre line, zero net mass flux through the diffuse wall, App. A.4), so
+    the steady state reached from a seed depends on its mass."""
+    t = np.array(table, dtype=np.float64)
+    c = n0 * np.sum(dx) / np.sum(t[:, 0] * dx)
+    for k in (0, 5, 6, 7, 8, 9, 10, 11, 12, 13):
+        t[:, k] *= c
+    return t
 
 
 def features(kn, u_w, omega, pr, x_half):

@@ -870,9 +870,9 @@ int hrlb_set_state(hrlb_sim* s, const double* d_in) {
   return HRLB_OK;
 }
 
-int hrlb_seed_state(hrlb_sim* s, const double* d_table, int* h_fallback) {
+int hrlb_seed_state(hrlb_sim* s, const double* d_table, int preserve_mass, int* h_fallback) {
   if (!s || !d_table) return fail(HRLB_EINVAL, "seed_state: NULL argument");
-  hipError_t e = (hipError_t)launch_seed(s->sh, s->d, d_table, s->stream);
+  hipError_t e = (hipError_t)launch_seed(s->sh, s->d, d_table, preserve_mass ? 1 : 0, s->stream);
   if (e != hipSuccess) return hip_fail(e, "seed_state: launch");
   if (h_fallback)
     HIP_TRY(hipMemcpyAsync(h_fallback, s->d.flags, s->sh.B * sizeof(int), hipMemcpyDeviceToHost, s->stream),

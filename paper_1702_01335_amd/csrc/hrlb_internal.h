@@ -100,7 +100,7 @@ int set_error(int code, const char* msg);
 
 int launch_setup_tables(const Shape& sh, const DevPtrs& d, void* stream);
 int launch_init_state(const Shape& sh, const DevPtrs& d, const double* perturb, double eps, void* stream);
-int launch_seed(const Shape& sh, const DevPtrs& d, const double* tab, void* stream);
+int launch_seed(const Shape& sh, const DevPtrs& d, const double* tab, int preserve_mass, void* stream);
 int launch_clear_flags(const Shape& sh, const DevPtrs& d, void* stream);
 int launch_partials(const Shape& sh, const DevPtrs& d, const double* F, int cells, int waves, void* stream);
 int launch_closure(const Shape& sh, const DevPtrs& d, const double* Fin, int nvb, double* mom_out, void* stream);

@@ -213,16 +213,21 @@ __global__ void init_state_kernel(Shape sh, DevPtrs d, const double* __restrict_
 
 // ---------------------------------------------------------------------------------------
 // warm-start seed from a moment table (per node: n, ux, uy, uz, T, Pxx, Pyy, Pzz, Pxy, Pxz,
-// Pyz, qx, qy, qz):  F = F^eq(n, u, T) (1 + Pi_ab xi_a xi_b / (2 n T^2)
-//                                     + (xi^2 / (5T) - 1) xi.q / (n T^2)),
+// Pyz, qx, qy, qz):  F = c F^eq(n, u, T) (1 + Pi_ab xi_a xi_b / (2 n T^2)
+//                                       + (xi^2 / (5T) - 1) xi.q / (n T^2)),
 // Pi_ab = P_ab - n T delta_ab, xi = p - u.  F^eq is the projected discrete equilibrium
 // (Sec. III) and the heat-flux polynomial is that of the Shakhov factor (Eq. sdef) with
-// 1 - Pr replaced by 1.  An instance with a node that is not finite or has n <= 0 or
-// T <= 0 is seeded with the equilibrium at rest instead (flags[b] = 1).
+// 1 - Pr replaced by 1.  c = 1, or with preserve_mass the per-instance factor that gives
+// the seed the mass of the equilibrium start, c = n0 sum_s dx_s / sum_s n_s dx_s (the
+// scheme conserves mass, so the steady state is fixed by it).  An instance with a node that
+// is not finite or has n <= 0 or T <= 0 is seeded with the equilibrium at rest instead
+// (flags[b] = 1).  The factor c travels in nw[b], which the first closure of the next step
+// recomputes before anything reads it.
 
 constexpr int TAB = 14;
 
-__global__ void __launch_bounds__(256) seed_check_kernel(Shape sh, DevPtrs d, const double* __restrict__ tab) {
+__global__ void __launch_bounds__(256) seed_check_kernel(Shape sh, DevPtrs d, const double* __restrict__ tab,
+                                                         int preserve_mass) {
   const int b = blockIdx.x;
   int bad = 0;
   for (int idx = threadIdx.x; idx < sh.S * TAB; idx += blockDim.x) {
@@ -231,7 +236,27 @@ __global__ void __launch_bounds__(256) seed_check_kernel(Shape sh, DevPtrs d, co
     if (!isfinite(x) || ((c == 0 || c == 4) && !(x > 0.0))) bad = 1;
   }
   bad = __syncthreads_or(bad);
-  if (threadIdx.x == 0) d.flags[b] = bad;
+  __shared__ double red[2][256];
+  double m = 0.0, len = 0.0;
+  for (int s = threadIdx.x; s < sh.S; s += blockDim.x) {
+    const double dx = 1.0 / d.inv_dx[(size_t)b * sh.S + s];
+    m += tab[((size_t)b * sh.S + s) * TAB] * dx;
+    len += dx;
+  }
+  red[0][threadIdx.x] = m;
+  red[1][threadIdx.x] = len;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    d.flags[b] = bad;
+    d.nw[b] = (preserve_mass && !bad) ? d.inst[b].n0 * red[1][0] / red[0][0] : 1.0;
+  }
 }
 
 __global__ void __launch_bounds__(256) seed_kernel(Shape sh, DevPtrs d, const double* __restrict__ tab) {
@@ -244,7 +269,7 @@ __global__ void __launch_bounds__(256) seed_kernel(Shape sh, DevPtrs d, const do
   }
   __shared__ double gx[2 * QX_MAX], gy[QYZ_MAX], gz[QYZ_MAX];
   const double* t = tab + (size_t)node * TAB;
-  const double n = t[0], ux = t[1], uy = t[2], uz = t[3], T = t[4];
+  const double n = t[0], ux = t[1], uy = t[2], uz = t[3], T = t[4], scale = d.nw[b];
   {
     double I[NX_MAX + 1], Jp[NX_MAX + 1], Jm[NX_MAX + 1], ay[NYZ_MAX + 1], az[NYZ_MAX + 1];
     half_gauss_moments(ux, T, I);
@@ -253,7 +278,8 @@ __global__ void __launch_bounds__(256) seed_kernel(Shape sh, DevPtrs d, const do
     half_projection(d.cx, sh.Nx, I, Jm);
     full_coeffs(uy, T, ay);
     full_coeffs(uz, T, az);
-    for (int i = threadIdx.x; i < 2 * sh.Qx; i += blockDim.x) gx[i] = n * gx_node(d.phix, sh.Qx, sh.Nx, i, Jp, Jm);
+    for (int i = threadIdx.x; i < 2 * sh.Qx; i += blockDim.x)
+      gx[i] = scale * n * gx_node(d.phix, sh.Qx, sh.Nx, i, Jp, Jm);
     for (int j = threadIdx.x; j < sh.Qy; j += blockDim.x) gy[j] = full_node(d.phiy, sh.Ny, j, ay);
     for (int k = threadIdx.x; k < sh.Qz; k += blockDim.x) gz[k] = full_node(d.phiz, sh.Nz, k, az);
   }
@@ -839,9 +865,9 @@ int launch_init_state(const Shape& sh, const DevPtrs& d, const double* perturb, 
   return (int)hipGetLastError();
 }
 
-int launch_seed(const Shape& sh, const DevPtrs& d, const double* tab, void* stream) {
+int launch_seed(const Shape& sh, const DevPtrs& d, const double* tab, int preserve_mass, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(seed_check_kernel, dim3(sh.B), dim3(256), 0, st, sh, d, tab);
+  hipLaunchKernelGGL(seed_check_kernel, dim3(sh.B), dim3(256), 0, st, sh, d, tab, preserve_mass);
   hipLaunchKernelGGL(seed_kernel, dim3(sh.B * sh.S), dim3(256), 0, st, sh, d, tab);
   return (int)hipGetLastError();
 }

@@ -40,6 +40,7 @@ constexpr int NPADR = (NPAD + 63) / 64 * 64;
 constexpr int MAX_ROWS = 1 << 22;
 constexpr int LOSS_BLOCKS = 1024;
 constexpr int LDR = 40;  // LDS row of a 32-wide K step, padded (bf16 elements; 80 bytes)
+constexpr int SPLIT_MAX = 16;  // K slices of a split weight-gradient product
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -172,16 +173,38 @@ __global__ void __launch_bounds__(256) loss_final_kernel(const float* __restrict
   if (threadIdx.x == 0) loss[0] = (float)(red[0] / ((double)rows * OUT));
 }
 
-// bias gradient: column sums of dZ[rows][n], 64 columns per block, 4 row phases
-__global__ void __launch_bounds__(256) colsum_kernel(const bf16* __restrict__ dz, int rows, int n, float* db) {
+// bias gradient: column sums of dZ[rows][n].  Block (x, y) sums 64 columns over the y-th
+// slice of rows (4 row phases, then a fixed-order LDS sum) into part[y][n]; a second
+// kernel adds the slices in order.
+__global__ void __launch_bounds__(256) colsum_kernel(const bf16* __restrict__ dz, int rows, int n, int slice,
+                                                     float* part) {
   const int c = blockIdx.x * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * slice, r1 = min(rows, r0 + slice);
   float s = 0.0f;
   if (c < n)
-    for (int r = g; r < rows; r += 4) s += (float)dz[(size_t)r * n + c];
+    for (int r = r0 + g; r < r1; r += 4) s += (float)dz[(size_t)r * n + c];
   __shared__ float red[256];
   red[threadIdx.x] = s;
   __syncthreads();
-  if (g == 0 && c < n) db[c] = ((red[threadIdx.x] + red[threadIdx.x + 64]) + red[threadIdx.x + 128]) + red[threadIdx.x + 192];
+  if (g == 0 && c < n)
+    part[(size_t)blockIdx.y * n + c] =
+        ((red[threadIdx.x] + red[threadIdx.x + 64]) + red[threadIdx.x + 128]) + red[threadIdx.x + 192];
+}
+
+__global__ void colsum_reduce_kernel(const float* __restrict__ part, int nslices, int n, float* db) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  float s = 0.0f;
+  for (int y = 0; y < nslices; ++y) s += part[(size_t)y * n + c];
+  db[c] = s;
+}
+
+hipError_t colsum(const bf16* dz, int rows, int n, float* ws, float* db, hipStream_t st) {
+  // at most 256 slices, so the partials fit the split-K workspace (256 x n <= SPLIT_MAX x 256 x 256)
+  const int slice = std::max(64, (rows + 255) / 256), ns = (rows + slice - 1) / slice;
+  hipLaunchKernelGGL(colsum_kernel, dim3((n + 63) / 64, ns), dim3(256), 0, st, dz, rows, n, slice, ws);
+  hipLaunchKernelGGL(colsum_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, st, ws, ns, n, db);
+  return hipGetLastError();
 }
 
 // raw outputs y * std + mean, as fp32 rows or as an fp64 Couette moment table
@@ -234,31 +257,54 @@ struct Gemm {
   int ldc;
   bf16* H;             // EPI_HIDDEN (silu z), EPI_DSILU (dz): H[i ldh + j]
   int ldh;
+  int kc;              // K values per slice (set by the launcher)
+  float* part;         // split-K partial products [slices][M][N], or NULL
 };
 
-// eight consecutive K elements of one operand row into LDS, zero beyond the matrix
-__device__ __forceinline__ void stage8(const bf16* __restrict__ base, long long srow, long long sk, bool row_ok,
-                                       int k, int K, bf16* dst) {
-  if (row_ok && sk == 1 && k + 8 <= K && ((((uintptr_t)(base + k)) & 15) == 0)) {
-    *(bf16x8*)dst = *(const bf16x8*)(base + k);
-    return;
-  }
+// One 64 x 32 operand tile (64 rows of the operand, 32 K values) into LDS as [row][k],
+// zero beyond the matrix.  Two access patterns, chosen per launch: with K contiguous each
+// thread loads 8 consecutive K values of one row; with rows contiguous (a transposed
+// operand) each thread loads 8 consecutive rows at one K value and scatters them.
+// 16-byte vector loads where the whole vector is inside the matrix and aligned.
+__device__ __forceinline__ void stage_tile(const bf16* __restrict__ base, long long srow, long long sk, int row0,
+                                           int nrows, int k0, int K, bf16* lds) {
+  const int tid = threadIdx.x;
+  if (sk == 1 || srow != 1) {
+    const int r = tid >> 2, kc = (tid & 3) * 8, row = row0 + r, k = k0 + kc;
+    bf16* dst = lds + r * LDR + kc;
+    const bool row_ok = row < nrows;
+    const bf16* src = base + (row_ok ? (long long)row * srow : 0);
+    if (row_ok && sk == 1 && k + 8 <= K && ((((uintptr_t)(src + k)) & 15) == 0)) {
+      *(bf16x8*)dst = *(const bf16x8*)(src + k);
+      return;
+    }
 #pragma unroll
-  for (int e = 0; e < 8; ++e) dst[e] = (row_ok && k + e < K) ? base[(long long)(k + e) * sk] : (bf16)0.0f;
-  (void)srow;
+    for (int e = 0; e < 8; ++e) dst[e] = (row_ok && k + e < K) ? src[(long long)(k + e) * sk] : (bf16)0.0f;
+  } else {
+    const int kk = tid >> 3, rc = (tid & 7) * 8, k = k0 + kk, row = row0 + rc;
+    bf16* dst = lds + rc * LDR + kk;
+    const bool k_ok = k < K;
+    const bf16* src = base + (k_ok ? (long long)k * sk : 0);
+    if (k_ok && row + 8 <= nrows && ((((uintptr_t)(src + row)) & 15) == 0)) {
+      const bf16x8 v = *(const bf16x8*)(src + row);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) dst[e * LDR] = v[e];
+      return;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dst[e * LDR] = (k_ok && row + e < nrows) ? src[row + e] : (bf16)0.0f;
+  }
 }
 
+// blockIdx.z selects a slice of K of kc values (a multiple of 32); with more than one slice
+// the raw products go to part[z][M][N] and a second kernel adds the slices in order.
 template <int EPI>
 __global__ void __launch_bounds__(256) gemm_kernel(Gemm g) {
   __shared__ __attribute__((aligned(16))) bf16 As[64 * LDR];
   __shared__ __attribute__((aligned(16))) bf16 Bs[64 * LDR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-  const int lr = tid >> 2, lk = (tid & 3) * 8;
-  const int ia = i0 + lr, jb = j0 + lr;
-  const bool a_ok = ia < g.M, b_ok = jb < g.N;
-  const bf16* arow = g.A + (a_ok ? (long long)ia * g.sar : 0);
-  const bf16* bcol = g.B + (b_ok ? (long long)jb * g.sbj : 0);
+  const int kbeg = blockIdx.z * g.kc, kend = min(g.K, kbeg + g.kc);
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int fr = lane & 15, fk = (lane >> 4) * 8;
   f32x4 acc[2][2];
@@ -266,9 +312,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(Gemm g) {
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k0 = 0; k0 < g.K; k0 += 32) {
-    stage8(arow, g.sar, g.sac, a_ok, k0 + lk, g.K, &As[lr * LDR + lk]);
-    stage8(bcol, g.sbj, g.sbk, b_ok, k0 + lk, g.K, &Bs[lr * LDR + lk]);
+  for (int k0 = kbeg; k0 < kend; k0 += 32) {
+    stage_tile(g.A, g.sar, g.sac, i0, g.M, k0, kend, As);
+    stage_tile(g.B, g.sbj, g.sbk, j0, g.N, k0, kend, Bs);
     __syncthreads();
     const bf16x8 a0 = *(const bf16x8*)&As[(wm + fr) * LDR + fk];
     const bf16x8 a1 = *(const bf16x8*)&As[(wm + 16 + fr) * LDR + fk];
@@ -280,6 +326,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(Gemm g) {
     acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
     __syncthreads();
   }
+  float* part = g.part ? g.part + (size_t)blockIdx.z * g.M * g.N : nullptr;
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -298,17 +345,43 @@ __global__ void __launch_bounds__(256) gemm_kernel(Gemm g) {
           g.C[(size_t)i * g.ldc + j] = v + g.bias[j];
         } else if (EPI == EPI_DSILU) {
           g.H[(size_t)i * g.ldh + j] = (bf16)(v * silu_grad(g.zin[(size_t)i * g.ldz + j]));
+        } else if (part) {
+          part[(size_t)i * g.N + j] = v;
         } else {
           g.C[(size_t)i * g.ldc + j] = v;
         }
       }
 }
 
+// C[i][j] = sum over slices z (in order) of part[z][i][j]
+__global__ void splitk_reduce_kernel(const float* __restrict__ part, int nz, int M, int N, float* C, int ldc) {
+  const int total = M * N;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (int z = 0; z < nz; ++z) s += part[(size_t)z * total + e];
+    C[(size_t)(e / N) * ldc + e % N] = s;
+  }
+}
+
 template <int EPI>
-hipError_t gemm(const Gemm& g, hipStream_t st) {
+hipError_t gemm(Gemm g, hipStream_t st, float* split_ws = nullptr) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+  int nz = 1;
+  // long reductions over few output tiles (the weight gradients): split K so the grid
+  // fills the chip; the slices are added by a second kernel in a fixed order
+  const int tiles = ((g.N + 63) / 64) * ((g.M + 63) / 64);
+  if (EPI == EPI_STORE && split_ws && tiles < 256 && g.K > 512) {
+    nz = std::min(SPLIT_MAX, std::max(1, 256 / tiles));
+    nz = std::min(nz, (g.K + 255) / 256);
+  }
+  g.kc = ((g.K + nz - 1) / nz + 31) / 32 * 32;
+  nz = (g.K + g.kc - 1) / g.kc;
+  g.part = nz > 1 ? split_ws : nullptr;
+  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, nz);
   hipLaunchKernelGGL(gemm_kernel<EPI>, grid, dim3(256), 0, st, g);
+  if (nz > 1)
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(std::min(1024, (g.M * g.N + 255) / 256)), dim3(256), 0, st, split_ws,
+                       nz, g.M, g.N, g.C, g.ldc);
   return hipGetLastError();
 }
 
@@ -347,6 +420,7 @@ struct hrlb_mlp {
   float* grad;
   float* part;
   float* loss;
+  float* split;
   int max_rows;
   long long t;
   hipStream_t stream;
@@ -359,7 +433,8 @@ size_t state_bytes_of() { return 3 * a256((size_t)NPADR * 4) + a256((size_t)NPAD
 size_t work_bytes_of(int rows) {
   const size_t Mp = ((size_t)rows + 63) / 64 * 64;
   return a256(Mp * K0 * 2) + 3 * a256(Mp * WID * 4) + 3 * a256(Mp * WID * 2) + a256(Mp * OUT * 4) +
-         a256(Mp * OUT * 2) + 2 * a256(Mp * WID * 2) + a256((size_t)NPADR * 4) + a256(LOSS_BLOCKS * 4) + 256;
+         a256(Mp * OUT * 2) + 2 * a256(Mp * WID * 2) + a256((size_t)NPADR * 4) + a256(LOSS_BLOCKS * 4) + 256 +
+         a256((size_t)SPLIT_MAX * WID * WID * 4);
 }
 
 hipError_t set_norm(hrlb_mlp* m, const float* h_norm) {
@@ -422,8 +497,8 @@ hipError_t backward(hrlb_mlp* m, const float* t, const int* idx, int rows, float
     Gemm g = make(m->dy, 1, OUT, m->h[2], WID, 1, OUT, WID, rows);
     g.C = m->grad + OW3;
     g.ldc = WID;
-    if (e == hipSuccess) e = gemm<EPI_STORE>(g, st);
-    hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, st, m->dy, rows, OUT, m->grad + OB3);
+    if (e == hipSuccess) e = gemm<EPI_STORE>(g, st, m->split);
+    if (e == hipSuccess) e = colsum(m->dy, rows, OUT, m->split, m->grad + OB3, st);
     Gemm d = make(m->dy, OUT, 1, m->wbf + OW3, WID, 1, rows, WID, OUT);
     d.zin = m->z[2];
     d.ldz = WID;
@@ -440,8 +515,8 @@ hipError_t backward(hrlb_mlp* m, const float* t, const int* idx, int rows, float
     Gemm g = make(dz, 1, WID, hin, kin, 1, WID, kin, rows);
     g.C = m->grad + ow[l];
     g.ldc = kin;
-    e = gemm<EPI_STORE>(g, st);
-    hipLaunchKernelGGL(colsum_kernel, dim3(WID / 64), dim3(256), 0, st, dz, rows, WID, m->grad + ob[l]);
+    e = gemm<EPI_STORE>(g, st, m->split);
+    if (e == hipSuccess) e = colsum(dz, rows, WID, m->split, m->grad + ob[l], st);
     if (l > 0 && e == hipSuccess) {
       Gemm d = make(dz, WID, 1, m->wbf + ow[l], kin, 1, rows, WID, WID);
       d.zin = m->z[l - 1];
@@ -525,6 +600,8 @@ int hrlb_mlp_create(void* d_state, size_t state_bytes, void* d_work, size_t work
   m->part = (float*)w;
   w += a256(LOSS_BLOCKS * 4);
   m->loss = (float*)w;
+  w += 256;
+  m->split = (float*)w;
   hipError_t e = set_norm(m, h_norm);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(params_set_kernel, dim3(grid_for(NPADR)), dim3(256), 0, m->stream, d_params, seed, m->master,

@@ -57,6 +57,9 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1702_01335_amd.build`")
+    # torch brings its own HIP runtime; loading it first makes the library bind to that same
+    # runtime instead of a second copy that would not share torch's device context
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, dp, ip, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_size_t
     lib.hrlb_last_error.restype = ctypes.c_char_p
@@ -76,7 +79,7 @@ def load():
     lib.hrlb_residual.argtypes = [vp, dp]
     lib.hrlb_get_state.argtypes = [vp, vp]
     lib.hrlb_set_state.argtypes = [vp, vp]
-    lib.hrlb_seed_state.argtypes = [vp, vp, ip]
+    lib.hrlb_seed_state.argtypes = [vp, vp, ctypes.c_int, ip]
     lib.hrlb_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.hrlb_get_launch.argtypes = [vp, ip, ip]
     lib.hrlb_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ip, ip, dp]
@@ -220,14 +223,15 @@ class Solver:
         self._staged = F
         _check(load().hrlb_set_state(self.handle, ctypes.c_void_p(F.data_ptr())))
 
-    def seed_state(self, table):
+    def seed_state(self, table, preserve_mass=True):
         """Warm start from a moment table (torch float64 [B, S, 14] on the device, the
-        column order of moments()).  Returns the per-instance fallback flags (1 where the
-        table was invalid and the equilibrium at rest was used)."""
+        column order of moments()), scaled to the mass of the equilibrium start unless
+        preserve_mass is False.  Returns the per-instance fallback flags (1 where the table
+        was invalid and the equilibrium at rest was used)."""
         t = table.to(device=self.device, dtype=self.torch.float64).contiguous()
         assert tuple(t.shape) == (self.B, self.S, 14)
         fb = np.zeros(self.B, dtype=np.int32)
-        _check(load().hrlb_seed_state(self.handle, ctypes.c_void_p(t.data_ptr()),
+        _check(load().hrlb_seed_state(self.handle, ctypes.c_void_p(t.data_ptr()), 1 if preserve_mass else 0,
                                       fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
         return fb
 

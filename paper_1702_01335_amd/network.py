@@ -85,17 +85,22 @@ class Network:
         hrlb._check(load().hrlb_mlp_get_params(self.handle, _ptr(out)))
         return out
 
+    def _rows(self, fn, x, out):
+        # the library takes at most max_rows rows per call; larger inputs go in slices
+        for r0 in range(0, x.shape[0], self.max_rows):
+            n = min(self.max_rows, x.shape[0] - r0)
+            hrlb._check(fn(self.handle, _ptr(x[r0:r0 + n]), n, _ptr(out[r0:r0 + n])))
+        return out
+
     def forward(self, x):
         x = self._dev(x)
         out = self.torch.empty((x.shape[0], OUT), dtype=self.torch.float32, device=self.device)
-        hrlb._check(load().hrlb_mlp_forward(self.handle, _ptr(x), x.shape[0], _ptr(out)))
-        return out
+        return self._rows(load().hrlb_mlp_forward, x, out)
 
     def predict_table(self, x):
         x = self._dev(x)
         out = self.torch.empty((x.shape[0], 14), dtype=self.torch.float64, device=self.device)
-        hrlb._check(load().hrlb_mlp_predict_table(self.handle, _ptr(x), x.shape[0], _ptr(out)))
-        return out
+        return self._rows(load().hrlb_mlp_predict_table, x, out)
 
     def gradient(self, x, t, idx=None, rows=None):
         """(gradient [NPARAMS], loss [1]) on device for the selected rows."""
@@ -114,7 +119,7 @@ class Network:
                                                float(wd), _ptr(loss)))
 
     def __del__(self):
-        if getattr(self, 'handle', None) and hrlb._lib is not None:
+        if getattr(self, 'handle', None) and hrlb is not None and hrlb._lib is not None:
             try:
                 self.stream.synchronize()
             except Exception:

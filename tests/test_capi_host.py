@@ -143,4 +143,4 @@ def test_mlp_sizes_and_argument_checks():
     assert not h.value
     assert lib.hrlb_mlp_forward(None, fake, 4, fake) == hrlb.HRLB_EINVAL
     assert lib.hrlb_mlp_train_step(None, fake, fake, None, 4, 1e-3, 0.0, None) == hrlb.HRLB_EINVAL
-    assert lib.hrlb_seed_state(None, fake, None) == hrlb.HRLB_EINVAL
+    assert lib.hrlb_seed_state(None, fake, 1, None) == hrlb.HRLB_EINVAL

@@ -83,6 +83,16 @@ def test_gradient_matches_oracle(M):
         assert rel(a, b) <= 5e-2
 
 
+def test_forward_in_slices_beyond_max_rows():
+    params = f32(om.init_params(2))
+    net = network.Network(64, IDENT, params=flat(params))
+    X, _ = data(200, 3)
+    y = net.forward(X).cpu().numpy()
+    big = network.Network(256, IDENT, params=flat(params))
+    assert np.array_equal(y, big.forward(X).cpu().numpy())
+    assert np.array_equal(net.predict_table(X).cpu().numpy(), big.predict_table(X).cpu().numpy())
+
+
 def test_gradient_gathers_rows_by_index():
     params = f32(om.init_params(5))
     net = network.Network(512, IDENT, params=flat(params))
@@ -190,7 +200,7 @@ def test_seed_matches_oracle(case):
     B = 3
     s = hrlb.Solver(q, wl['S'], wl['scheme'], [hrlb.make_params(**wl['params'])] * B)
     tab = random_tables(np.random.default_rng(20 + case), B, wl['S'])
-    fb = s.seed_state(torch.from_numpy(tab).cuda())
+    fb = s.seed_state(torch.from_numpy(tab).cuda(), preserve_mass=False)
     assert not fb.any()
     F = s.get_state().cpu().numpy()
     m = sv.Model(oracle_params(wl))
@@ -204,6 +214,25 @@ def test_seed_matches_oracle(case):
     F3 = s.get_state().cpu().numpy()
     Fo = sv.run(ows.seed(tab[1], m.vs), m, 3)
     assert_parity(F3[1], Fo, m, "seeded state after 3 steps")
+
+
+def test_mass_preserving_seed_matches_oracle():
+    # with full-range orders >= 3 the correction terms carry no mass, so the seed's mass is
+    # the scaled table's
+    wl = make_wl(5, 4, 4, 13, 'weno5', A=0.9, dt=1e-4)
+    q = hrlb.Quadrature(wl['Qx'], wl['Qy'], wl['Qz'])
+    B = 2
+    p = dict(wl['params'])
+    p['n0'] = 1.2
+    s = hrlb.Solver(q, wl['S'], wl['scheme'], [hrlb.make_params(**p)] * B)
+    tab = random_tables(np.random.default_rng(40), B, wl['S'])
+    s.seed_state(torch.from_numpy(tab).cuda(), preserve_mass=True)
+    F = s.get_state().cpu().numpy()
+    m = sv.Model(oracle_params(wl, p))
+    for b in range(B):
+        Fo = ows.seed(ows.mass_preserving(tab[b], m.dx, 1.2), m.vs)
+        assert_parity(F[b], Fo, m, f"mass-preserving seed {b}")
+        assert abs(np.sum(F[b].sum(axis=1) * m.dx) - 1.2 * np.sum(m.dx)) <= 1e-13
 
 
 def test_seed_falls_back_to_equilibrium_for_invalid_tables():
@@ -225,3 +254,16 @@ def test_seed_falls_back_to_equilibrium_for_invalid_tables():
     assert not np.array_equal(F[0], F_eq[0])
     s.step(2)
     assert np.all(np.isfinite(s.residual()))
+
+
+def test_gradient_with_many_rows_matches_oracle():
+    """Long reductions (split K slices, many bias-gradient row slices) at 20000 rows."""
+    params = f32(om.init_params(14))
+    net = network.Network(20000, IDENT, params=flat(params))
+    X, T = data(20000, 15)
+    g, loss = net.gradient(X, T)
+    g = unflat(g.cpu().numpy())
+    Lo, go = om.loss_and_grad(params, X.astype(np.float64), T.astype(np.float64), quant=True)
+    assert abs(loss.item() - Lo) <= 1e-3 * Lo
+    for k, (a, b) in enumerate(zip(g, go)):
+        assert rel(a, b) <= 1e-2, k

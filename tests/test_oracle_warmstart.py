@@ -76,3 +76,22 @@ def test_profile_table_round_trip():
     assert np.array_equal(ws.table_from_profiles(ws.profiles_from_table(tab)), tab)
     T = tab[:, 4]
     assert np.allclose(tab[:, 5] + tab[:, 6] + tab[:, 7], 3 * tab[:, 0] * T, rtol=1e-15)
+
+
+def test_mass_preserving_scale():
+    p = sv.Params(Qx=5, Qy=4, Qz=4, S=11, dt=1e-3, A=0.9, n0=1.3)
+    m = sv.Model(p)
+    rng = np.random.default_rng(6)
+    tab = ws.table_from_profiles(np.stack([rng.uniform(0.8, 1.2, p.S), rng.uniform(-0.2, 0.2, p.S),
+                                           rng.uniform(0.9, 1.1, p.S), np.ones(p.S), 0.01 * np.ones(p.S),
+                                           np.ones(p.S), 0.01 * np.ones(p.S), -0.01 * np.ones(p.S)], axis=-1))
+    scaled = ws.mass_preserving(tab, m.dx, p.n0)
+    f = ws.seed(scaled, m.vs)
+    mass = np.sum(f.sum(axis=1) * m.dx)
+    assert abs(mass - p.n0 * np.sum(m.dx)) <= 1e-14 * mass
+    # the equilibrium start has that mass too
+    assert abs(np.sum(sv.equilibrium_state(m).sum(axis=1) * m.dx) - mass) <= 1e-14 * mass
+    # u and T are intensive: unchanged
+    m0, m1 = sv.moments(ws.seed(tab, m.vs), m), sv.moments(f, m)
+    assert np.allclose(m0.u[1], m1.u[1], rtol=1e-13, atol=1e-15) and np.allclose(m0.T, m1.T, rtol=1e-13)
+    assert np.allclose(ws.seed(scaled, m.vs), ws.seed(tab, m.vs) * scaled[0, 0] / tab[0, 0], rtol=1e-13)
