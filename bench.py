@@ -43,6 +43,10 @@ def parse():
     ap.add_argument('--no-sweep', action='store_true', help='skip the ragged-sweep measurements')
     ap.add_argument('--sweep-instances', type=int, default=256)
     ap.add_argument('--steady-instances', type=int, default=16)
+    ap.add_argument('--no-warm', action='store_true', help='skip the learned warm-start measurement')
+    ap.add_argument('--warm-train', type=int, default=1000, help='instances whose steady states train the network')
+    ap.add_argument('--warm-heldout', type=int, default=100)
+    ap.add_argument('--warm-steps', type=int, default=10000, help='AdamW steps of the network')
     return ap.parse_args()
 
 
@@ -161,6 +165,31 @@ def sweep_section(n_inst, n_steady, steps):
     return out
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def warm_section(n_train, n_heldout, train_steps):
+    """Learned warm start: n_train instances of the sweep distribution (one velocity set and
+    grid: Qx = 8, Qy = Qz = 5, S = 64, upwind2) run to residual 1e-10 as one batch give the
+    training rows; the network is trained on the GPU by the library's kernels; n_heldout
+    instances of another seed are run to 1e-10 from the equilibrium start and from the
+    warm start."""
+    import numpy as np
+    from paper_1702_01335_amd import warmstart as ws
+    X, Y, info = ws.collect(n_train, 20170205)
+    progress(f"warm start: collected {info['rows']} rows in {info['wall_s']:.1f} s")
+    net, log, t_train = ws.train(X, Y, steps=train_steps)
+    flop = 3 * 2 * 4096 * (5 * 256 + 2 * 256 * 256 + 256 * 8) * train_steps
+    progress(f"warm start: trained {train_steps} steps in {t_train:.1f} s, loss {log[-1][1]:.2e}")
+    res = ws.compare(net, n_heldout, 20170206)
+    st_p, st_w = np.array(res.pop('steps_plain')), np.array(res.pop('steps_warm'))
+    return dict(collect=info, train=dict(steps=train_steps, batch=4096, wall_s=t_train, loss_first=log[0][1],
+                                         loss_last=log[-1][1], tflops=flop / t_train / 1e12,
+                                         frac_bf16_peak=flop / t_train / 2.5e15),
+                heldout=res)
+
+
 def cpu_baseline(wl, seconds):
     """The oracle (numpy, FP64, single-threaded) on one instance of the workload for a
     bounded number of steps; returns pair-updates per second."""
@@ -259,10 +288,16 @@ def main():
         'residual_max': float(res.max()),
         'wall_s_timed': wall,
     }
-    if not args.no_sweep:
+    progress(f"step: {value:.2f} G pair-updates/s, stage kernel {stage_avg_s * 1e6:.1f} us")
+    if not args.no_sweep or not args.no_warm:
         del solver
         torch.cuda.empty_cache()
+    if not args.no_sweep:
         out['sweep'] = sweep_section(args.sweep_instances, args.steady_instances, min(args.steps, 50))
+        progress(f"sweep: {out['sweep']['value']:.2f} G pair-updates/s batched")
+    if not args.no_warm:
+        out['warm_start'] = warm_section(args.warm_train, args.warm_heldout, args.warm_steps)
+        progress(f"warm start: wall ratio {out['warm_start']['heldout']['wall_ratio']:.3f}")
     if not args.no_cpu:
         out['cpu_baseline'] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
