@@ -341,9 +341,10 @@ __device__ __forceinline__ dbl4 moment_mfma(const double* ft, const double* a, i
 // the multipliers of the wave's velocities (A operands loaded here, from the small,
 // cache-resident multiplier table, so they hold no registers during the march), sum over
 // the block's waves and write the block's partials for nodes s .. s+cnt-1.
-__device__ __forceinline__ void flush_group(double* lds_ft, double* lds_red, const double* __restrict__ ptab,
-                                            int wave_v0, int V, int wave, int waves, int lane, int cnt,
-                                            double* __restrict__ out, int node_stride) {
+// contract the wave tiles of 16 node rows with the moment multipliers (matrix cores) into
+// lds_red[wave][node][16]
+__device__ __forceinline__ void moment_contract(double* lds_ft, double* lds_red, const double* __restrict__ ptab,
+                                                int wave_v0, int V, int wave, int lane) {
   double a[16];
   load_moment_operands(ptab, wave_v0, V, lane, a);
   __syncthreads();
@@ -354,12 +355,24 @@ __device__ __forceinline__ void flush_group(double* lds_ft, double* lds_red, con
   r[8] = acc[2];
   r[12] = acc[3];
   __syncthreads();
+}
+
+// sum the waves' contractions of cnt nodes and store them, node-major with node_stride
+__device__ __forceinline__ void store_moments(const double* lds_red, int waves, int cnt, double* __restrict__ out,
+                                              int node_stride) {
   for (int idx = threadIdx.x; idx < cnt * NMOM; idx += blockDim.x) {
     const int n = idx / NMOM, q = idx - n * NMOM;
     double s = 0.0;
     for (int w = 0; w < waves; ++w) s += lds_red[w * RED_WAVE + n * 16 + q];
     out[(size_t)n * node_stride + q] = s;
   }
+}
+
+__device__ __forceinline__ void flush_group(double* lds_ft, double* lds_red, const double* __restrict__ ptab,
+                                            int wave_v0, int V, int wave, int waves, int lane, int cnt,
+                                            double* __restrict__ out, int node_stride) {
+  moment_contract(lds_ft, lds_red, ptab, wave_v0, V, wave, lane);
+  store_moments(lds_red, waves, cnt, out, node_stride);
 }
 
 __global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, const double* __restrict__ F, int nvb,
@@ -627,6 +640,9 @@ __device__ __forceinline__ double stencil_flux(bool pos, double px, double w0, d
 }
 
 // one tile: instance b, velocity block vb (64 * waves velocities), node chunk ch (cs nodes)
+// depth of the stage kernel's load pipeline (nodes ahead); divides 16
+constexpr int PIPE = 4;
+
 template <int SCHEME, int STAGE>
 __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, const double* __restrict__ Fin,
                                            const double* Fl, double* Fout, int b, int vb, int ch, int nvb, int nch,
@@ -673,35 +689,40 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   W5 = ghost_node(W5, s0 + 2, S, pos, W4, W3, W2, ex, ghost_in);
   double fl = stencil_flux<SCHEME>(pos, px, W0, W1, W2, W3, W4, W5);
 
-  // Per-node operands, software-pipelined two nodes ahead in two alternating register
-  // sets (the node loop is unrolled by two, so no register with a load in flight is ever
-  // copied).  All are unconditional vector loads, which complete in order: the window node
-  // c+3, F_l, the two equilibrium-factor gathers, and the node's uniform closure scalars
-  // (lane q < 9 loads record field q: u, 1/tau, Shakhov coefficients, q; lane 9 loads
-  // 1/dx), broadcast with readlane where used.
-  struct Ops {
-    double raw, fl0, gx, gyz, sc;
+  // Per-node operands, software-pipelined in rotating register sets (the node loop is
+  // unrolled by PIPE, so no register with a load in flight is ever copied).  The two HBM
+  // streams, the window node c+3 and F_l, run PIPE nodes ahead; the gathers that hit the
+  // cache (the two equilibrium factors and the node's uniform closure scalars: lane q < 9
+  // loads record field q -- u, 1/tau, Shakhov coefficients, q -- and lane 9 loads 1/dx,
+  // broadcast with readlane where used) run two nodes ahead.  All are unconditional
+  // vector loads with clamped addresses, which complete in order.
+  struct Far {
+    double raw, fl0;
+  };
+  struct Near {
+    double gx, gyz, sc;
   };
   const int clast = s0 + nloc - 1;
   const int gx_off = REC_HEAD + i, gyz_off = REC_HEAD + 2 * Qx + jk;
   const int sq = lane < 9 ? lane : 0;
-  auto ld_ops = [&](int c, Ops& o) {
-    const int cc = min(c, clast);
-    const double* rec = recb + (size_t)cc * sh.rec_len;
+  auto ld_far = [&](int c, Far& o) {
     o.raw = raw_node(Fb, c + 3, S, V, vv, vm);
     if constexpr (STAGE != 1)
-      o.fl0 = Fl[base + (size_t)cc * V + vv];
+      o.fl0 = Fl[base + (size_t)min(c, clast) * V + vv];
     else
       o.fl0 = 0.0;
+  };
+  auto ld_near = [&](int c, Near& o) {
+    const int cc = min(c, clast);
+    const double* rec = recb + (size_t)cc * sh.rec_len;
     o.gx = rec[gx_off];
     o.gyz = rec[gyz_off];
     const double* sp = (lane == 9) ? invdx + cc : rec + sq;
     o.sc = *sp;
   };
   double rd = 0.0, rf = 0.0;
-  double* junk = d.junk + threadIdx.x;  // store target of lanes beyond V
   // one node: complete the window, flux, collision, RK combine, store; returns F_out
-  auto node = [&](int c, const Ops& o) -> double {
+  auto node = [&](int c, const Far& o, const Near& p) -> double {
     const double Wn = ghost_node(o.raw, c + 3, S, pos, W5, W4, W3, ex, ghost_in);
     W0 = W1;
     W1 = W2;
@@ -709,12 +730,12 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
     W3 = W4;
     W4 = W5;
     W5 = Wn;
-    const double scc = o.sc;
+    const double scc = p.sc;
     const double fr = stencil_flux<SCHEME>(pos, px, W0, W1, W2, W3, W4, W5);
     const double D = (fr - fl) * bcast(scc, 9);  // Eq. flux
     fl = fr;
     const double F = W2;
-    const double feq = o.gx * o.gyz;
+    const double feq = p.gx * p.gyz;
     const double Cs = bcast(scc, 4);
     double FS = feq;
     if (Cs != 0.0) {
@@ -736,33 +757,50 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
       rd += dlt * dlt;
       rf += flm * flm;
     }
-    double* dst = active ? Fout + base + (size_t)c * V + v : junk;
-    *dst = out;
     return active ? out : 0.0;
   };
-  Ops A, Bo;
-  ld_ops(s0, A);
-  ld_ops(s0 + 1, Bo);
+  Far far[PIPE];
+  Near near[PIPE];
+#pragma unroll
+  for (int k = 0; k < PIPE; ++k) {
+    ld_far(s0 + k, far[k]);
+    ld_near(s0 + k, near[k]);
+  }
 
+  int last_cnt = 0, last_g = 0;
   for (int g = 0; g < nloc; g += 16) {
     const int cnt = min(16, nloc - g);
-    int u = 0;
-    for (; u + 1 < cnt; u += 2) {
+    // the 16 nodes of a group as straight-line code (uniform guards for the last, partial
+    // group): the load counter's state is then known exactly at every wait, which a loop
+    // back-edge inside the group would blur into a full drain
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
       const int c = s0 + g + u;
-      ft[u * FT_LD + lane] = node(c, A);
-      ld_ops(c + 2, A);
-      ft[(u + 1) * FT_LD + lane] = node(c + 1, Bo);
-      ld_ops(c + 3, Bo);
+      double out = 0.0;
+      if (u < cnt) out = node(c, far[u % PIPE], near[u % PIPE]);
+      ft[u * FT_LD + lane] = out;
+      // the prefetches are issued on every path (clamped addresses): a load under a branch
+      // would have to be merged into one register at the join, and that copy would wait
+      // for the load
+      ld_far(c + PIPE, far[u % PIPE]);
+      ld_near(c + PIPE, near[u % PIPE]);
     }
-    if (u < cnt) {
-      // odd count: only at the end of the chunk (groups before the last hold 16 nodes)
-      ft[u * FT_LD + lane] = node(s0 + g + u, A);
-      ++u;
+    // Stores happen only here, once per 16 nodes: the group's results from the lane's own
+    // LDS column and the previous group's moment sums, right before the contraction waits
+    // for its operands.  Loads and stores share one counter, so any wait issued while a
+    // store is in flight drains everything; with the stores bunched here that single drain
+    // covers them and the prefetched loads together, and the march starts each group
+    // with no store outstanding, so its waits stay partial.
+    if (active) {
+      double* dst = Fout + base + (size_t)(s0 + g) * V + v;
+      for (int u = 0; u < cnt; ++u) dst[(size_t)u * V] = ft[u * FT_LD + lane];
     }
-    for (; u < 16; ++u) ft[u * FT_LD + lane] = 0.0;
-    flush_group(lds_ft, lds_red, d.ptab, wave_v0, V, wave, waves, lane, cnt, part + (size_t)g * nstride, nstride);
-    __syncthreads();
+    if (g > 0) store_moments(lds_red, waves, 16, part + (size_t)(g - 16) * nstride, nstride);
+    moment_contract(lds_ft, lds_red, d.ptab, wave_v0, V, wave, lane);
+    last_cnt = cnt;
+    last_g = g;
   }
+  store_moments(lds_red, waves, last_cnt, part + (size_t)last_g * nstride, nstride);
   if constexpr (STAGE == 3) {
     rd = wave_sum(rd);
     rf = wave_sum(rf);
