@@ -37,6 +37,7 @@ def parse():
     ap.add_argument('--waves', type=int, default=0)
     ap.add_argument('--no-cpu', action='store_true')
     ap.add_argument('--eager', action='store_true', help='launch kernels one by one instead of replaying a HIP graph')
+    ap.add_argument('--no-tune', action='store_true', help='keep the default launch shape instead of autotuning it')
     ap.add_argument('--copy-probe-mib', type=int, default=0,
                     help='also run one device copy of this size (calibrates HBM byte counters under a profiler)')
     ap.add_argument('--cpu-seconds', type=float, default=15.0)
@@ -82,9 +83,10 @@ def time_steps(solver, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def profiled_traffic(tag, bytes_per_launch):
+def profiled_traffic(tag, bytes_per_launch, cells, waves):
     """HBM bytes per stage-kernel launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    passes (profiles/<tag>_traffic.json), or None when the kernel source has changed since."""
+    passes (profiles/<tag>_traffic.json), or None when the kernel source or the launch shape
+    differs from the one profiled."""
     import hashlib
     path = os.path.join(ROOT, 'profiles', f'{tag}_traffic.json')
     if not os.path.exists(path):
@@ -92,6 +94,8 @@ def profiled_traffic(tag, bytes_per_launch):
     tr = json.load(open(path))
     src = open(os.path.join(ROOT, 'paper_1702_01335_amd', 'csrc', 'kernels.hip'), 'rb').read()
     if hashlib.sha256(src).hexdigest() != tr['kernel_source_sha256']:
+        return None
+    if tr.get('launch') != {'cells': cells, 'waves': waves}:
         return None
     ks = tr['stage_kernels'].values()
     t = sum(k['fetch_bytes'] + k['write_bytes'] for k in ks) / len(ks)
@@ -222,9 +226,14 @@ def main():
     device = 'cuda:0'
     torch.cuda.set_device(0)
     q, solver = make_solver(wl, args.batch, device)
+    tuned = None
     if args.cells or args.waves:
         c0, w0 = solver.get_launch()
         solver.set_launch(args.cells or c0, args.waves or w0)
+    elif not args.no_tune:
+        # the library's autotuner times every (node chunk, waves) shape on this state
+        c_t, w_t, ms_t = solver.autotune(probe_steps=3)
+        tuned = dict(cells=c_t, waves=w_t, probe_ms_per_step=ms_t)
     cells, waves = solver.get_launch()
     solver.set_graph(not args.eager)
     pairs = args.batch * wl['S'] * q.V
@@ -240,7 +249,7 @@ def main():
     closure_avg_s = tm['closure_ms'] / tm['closure_launches'] * 1e-3
     bytes_per_launch = pairs * BYTES_PER_PAIR_STEP / 3.0
     achieved = bytes_per_launch / stage_avg_s
-    traffic = profiled_traffic(f"stage_kernel_{args.workload}_b{args.batch}", bytes_per_launch)
+    traffic = profiled_traffic(f"stage_kernel_{args.workload}_b{args.batch}", bytes_per_launch, cells, waves)
     res = solver.residual()
 
     if args.copy_probe_mib:
@@ -275,7 +284,7 @@ def main():
         'config': {'workload': f"{args.workload} x {args.batch} independent seeded instances",
                    'batch': args.batch, 'S': wl['S'], 'V': q.V, 'Qx': wl['Qx'], 'Qy': wl['Qy'], 'Qz': wl['Qz'],
                    'scheme': wl['scheme'], 'pairs': pairs,
-                   'launch': {'cells': cells, 'waves': waves, 'graph': not args.eager},
+                   'launch': {'cells': cells, 'waves': waves, 'graph': not args.eager, 'autotuned': tuned},
                    'parallelism': 'single GPU'},
         'hbm_frac_step': pairs * BYTES_PER_PAIR_STEP / (ms * 1e-3) / HBM_PEAK,
         'roofline': {'bound': 'hbm', 'achieved': achieved / 1e9, 'peak': HBM_PEAK / 1e9, 'unit': 'GB/s',

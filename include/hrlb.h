@@ -44,9 +44,11 @@ extern "C" {
 
 #define HRLB_LAW_POWER 0      /* mu = kn T^omega  -> tau = kn T^(omega-1) / n  (Eq. mw_tau for omega = 1) */
 #define HRLB_LAW_SUTHERLAND 1 /* mu = kn sqrt(T)(1+S)/(1+S/T) -> Eq. sutherland_tau with kn = 1/(delta sqrt 2) */
+#define HRLB_LAW_LOWMACH 2    /* constant tau = kn / sqrt(2), kn = k: the linearised regime of Sec. IV, Eq. knLuo */
 
 #define HRLB_SCHEME_UPWIND2 0 /* second-order upwind fluxes                                  */
 #define HRLB_SCHEME_WENO5 1   /* epsilon-free WENO-5, Eqs. weno5_flux..weno_sigma, Table II  */
+#define HRLB_SCHEME_LINEAR5 2 /* the WENO-5 candidate fluxes with the ideal weights (linear fifth order) */
 
 /* Physical and numerical parameters of one Couette instance (non-dimensional, Sec. II.B). */
 typedef struct hrlb_params {

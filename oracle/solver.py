@@ -6,7 +6,8 @@ State: F[s, v], s = 1..S fluid nodes on the half channel 0 <= x <= L/2 (L = 1), 
 the right-hand side L[F] (Eq. L_def) takes these steps, in the paper's order:
 
 1. moments n, u, pressure tensor, T, q of F (Eq. qdef; P = n T);
-2. relaxation time tau (Eq. mw_tau; power law mu ~ T^omega of Sec. VI; Eq. sutherland_tau);
+2. relaxation time tau (Eq. mw_tau; power law mu ~ T^omega of Sec. VI; Eq. sutherland_tau;
+   the constant tau of the linearised regime, Eq. knLuo);
 3. Shakhov target F^eq (1 + S) (Eqs. phieq, sdef; discrete construction of Sec. III);
 4. ghost nodes: bounce-back at x = 0 (Eq. widetildei), quadratic extrapolation of the
    outgoing populations and diffuse-reflection wall Maxwellian with the wall density fixed
@@ -49,7 +50,8 @@ class Params:
 
     kn          rarefaction: viscosity mu(T) = kn * T^omega (power law) or Sutherland's
                 law scaled to mu(1) = kn (kn = 1/(delta sqrt 2) of Sec. VI).
-    law         'power' or 'sutherland'.
+    law         'power', 'sutherland' or 'lowmach' (constant tau = kn / sqrt 2, kn = k of
+                Sec. IV).
     collisionless  drop the collision term (1/tau = 0).
     A           tanh stretching parameter of Eq. stretch; A = 0 is the equidistant grid.
     scheme      'weno5', 'upwind2' or 'linear5' (WENO-5 stencils with the ideal weights; a
@@ -180,11 +182,14 @@ def relaxation_time(n, T, p: Params):
     """tau with mu = tau n T (Chapman-Enskog, Sec. II.A):
     power law mu = kn T^omega -> tau = kn T^(omega-1) / n (omega = 1: Eq. mw_tau);
     Sutherland (Eq. sutherland_tau with 1/(delta sqrt 2) = kn):
-        tau = kn (1 + S) / (n sqrt(T) (1 + S/T))."""
+        tau = kn (1 + S) / (n sqrt(T) (1 + S/T));
+    linearised low-Mach regime of Sec. IV (Eq. knLuo, kn = k): tau = k / sqrt(2), constant."""
     if p.law == 'power':
         return p.kn * T ** (p.omega - 1.0) / n
     if p.law == 'sutherland':
         return p.kn * (1.0 + p.suth_S) / (n * np.sqrt(T) * (1.0 + p.suth_S / T))
+    if p.law == 'lowmach':
+        return np.full_like(np.asarray(n, dtype=np.float64), p.kn / np.sqrt(2.0))
     raise ValueError(p.law)
 
 

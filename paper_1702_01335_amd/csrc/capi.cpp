@@ -235,7 +235,8 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
   if (!q || !params || !d_state || !d_work) return fail(HRLB_EINVAL, "init_state: NULL argument");
   if (S < 3) return fail(HRLB_EINVAL, "init_state: S must be >= 3 (three ghost layers mirror nodes 1..3)");
   if (batch < 1) return fail(HRLB_EINVAL, "init_state: batch must be >= 1");
-  if (scheme != HRLB_SCHEME_UPWIND2 && scheme != HRLB_SCHEME_WENO5) return fail(HRLB_EINVAL, "init_state: unknown scheme");
+  if (scheme != HRLB_SCHEME_UPWIND2 && scheme != HRLB_SCHEME_WENO5 && scheme != HRLB_SCHEME_LINEAR5)
+    return fail(HRLB_EINVAL, "init_state: unknown scheme");
   if (((uintptr_t)d_state & 255) || ((uintptr_t)d_work & 255))
     return fail(HRLB_EINVAL, "init_state: buffers must be 256-byte aligned");
   for (int b = 0; b < batch; ++b) {
@@ -247,7 +248,8 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
     if (!(p.n0 > 0)) return fail(HRLB_EINVAL, "init_state: n0 must be > 0" + at);
     if (!(p.pr > 0)) return fail(HRLB_EINVAL, "init_state: pr must be > 0" + at);
     if (!(p.A >= 0 && p.A < 1)) return fail(HRLB_EINVAL, "init_state: A must be in [0, 1)" + at);
-    if (p.law != HRLB_LAW_POWER && p.law != HRLB_LAW_SUTHERLAND) return fail(HRLB_EINVAL, "init_state: unknown law" + at);
+    if (p.law != HRLB_LAW_POWER && p.law != HRLB_LAW_SUTHERLAND && p.law != HRLB_LAW_LOWMACH)
+      return fail(HRLB_EINVAL, "init_state: unknown law" + at);
     if (p.law == HRLB_LAW_SUTHERLAND && !(p.suth_S >= 0)) return fail(HRLB_EINVAL, "init_state: suth_S must be >= 0" + at);
     if (!std::isfinite(p.u_w) || !std::isfinite(p.omega)) return fail(HRLB_EINVAL, "init_state: non-finite u_w/omega" + at);
   }

@@ -84,10 +84,20 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
   return (2.0 / 3.0) * f2 + (1.0 / 3.0) * f3;
 }
 
+// the WENO-5 candidates with the ideal weights: the linear fifth-order upwind flux
+__device__ __forceinline__ double linear5(double a, double b, double c, double d, double e) {
+  const double f1 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
+  const double f2 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
+  const double f3 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
+  return 0.1 * f1 + 0.6 * f2 + 0.3 * f3;
+}
+
 template <int SCHEME>
 __device__ __forceinline__ double interp(double a, double b, double c, double d, double e) {
   if constexpr (SCHEME == 1) {
     return weno5(a, b, c, d, e);
+  } else if constexpr (SCHEME == 2) {
+    return linear5(a, b, c, d, e);
   } else {
     (void)a;
     (void)d;
@@ -430,7 +440,9 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
       const double f3 = F[(size_t)(S - 3) * V + v], f2 = F[(size_t)(S - 2) * V + v], f1 = F[(size_t)(S - 1) * V + v];
       const double g0 = in->ex[0] * f1 + in->ex[1] * f2 + in->ex[2] * f3;
       const double g1 = in->ex[3] * g0 + in->ex[4] * f1 + in->ex[5] * f2;
-      const double r = (sh.scheme == 1) ? weno5(f3, f2, f1, g0, g1) : (1.5 * f1 - 0.5 * f2);
+      const double r = (sh.scheme == 1)   ? weno5(f3, f2, f1, g0, g1)
+                       : (sh.scheme == 2) ? linear5(f3, f2, f1, g0, g1)
+                                          : (1.5 * f1 - 0.5 * f2);
       acc += px * r;
     }
     acc = wave_sum(acc);
@@ -520,8 +532,10 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
     double tau;
     if (in->law == 0.0)
       tau = in->kn * pow(T, in->omega - 1.0) / n;
-    else
+    else if (in->law == 1.0)
       tau = in->kn * (1.0 + in->suth) / (n * sqrt(T) * (1.0 + in->suth / T));
+    else
+      tau = in->kn * M_SQRT1_2;  // linearised (low Mach) regime, Eq. knLuo: tau = k / sqrt(2)
     const double invtau = (in->collisionless != 0.0 || bad) ? 0.0 : 1.0 / tau;
     const double Cs = (1.0 - in->pr) / (n * T * T);
     double* rec = d.rec + (size_t)g * sh.rec_len;
@@ -842,6 +856,8 @@ __global__ void __launch_bounds__(256) batch_stage_kernel(const GroupDesc* __res
     double* Fout = g.d.F[STAGE % 3];
     if (g.sh.scheme == 1)
       stage_tile<1, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
+    else if (g.sh.scheme == 2)
+      stage_tile<2, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
     else
       stage_tile<0, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
     __syncthreads();
@@ -950,6 +966,11 @@ int launch_stage(const Shape& sh, const DevPtrs& d, int stage, const double* Fin
     if (stage == 1) return launch_stage_t<1, 1>(sh, d, Fin, Fl, Fout, cells, waves, stream);
     if (stage == 2) return launch_stage_t<1, 2>(sh, d, Fin, Fl, Fout, cells, waves, stream);
     return launch_stage_t<1, 3>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+  }
+  if (sh.scheme == 2) {
+    if (stage == 1) return launch_stage_t<2, 1>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+    if (stage == 2) return launch_stage_t<2, 2>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+    return launch_stage_t<2, 3>(sh, d, Fin, Fl, Fout, cells, waves, stream);
   }
   if (stage == 1) return launch_stage_t<0, 1>(sh, d, Fin, Fl, Fout, cells, waves, stream);
   if (stage == 2) return launch_stage_t<0, 2>(sh, d, Fin, Fl, Fout, cells, waves, stream);

@@ -14,10 +14,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, 'libhrlb.so')
 
 HRLB_OK, HRLB_EINVAL, HRLB_ENOMEM, HRLB_EHIP, HRLB_ENUMERIC = 0, -1, -2, -3, -4
-LAW_POWER, LAW_SUTHERLAND = 0, 1
-SCHEME_UPWIND2, SCHEME_WENO5 = 0, 1
-SCHEMES = {'upwind2': SCHEME_UPWIND2, 'weno5': SCHEME_WENO5}
-LAWS = {'power': LAW_POWER, 'sutherland': LAW_SUTHERLAND}
+LAW_POWER, LAW_SUTHERLAND, LAW_LOWMACH = 0, 1, 2
+SCHEME_UPWIND2, SCHEME_WENO5, SCHEME_LINEAR5 = 0, 1, 2
+SCHEMES = {'upwind2': SCHEME_UPWIND2, 'weno5': SCHEME_WENO5, 'linear5': SCHEME_LINEAR5}
+LAWS = {'power': LAW_POWER, 'sutherland': LAW_SUTHERLAND, 'lowmach': LAW_LOWMACH}
 MOMENT_NAMES = ('n', 'ux', 'uy', 'uz', 'T', 'Pxx', 'Pyy', 'Pzz', 'Pxy', 'Pxz', 'Pyz', 'qx', 'qy', 'qz')
 
 EXPORTS = ('hrlb_last_error', 'hrlb_init_quadrature', 'hrlb_quad_free', 'hrlb_quad_size', 'hrlb_quad_nodes',

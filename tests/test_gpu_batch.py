@@ -151,3 +151,18 @@ def test_sweep_plain_matches_batched_steps():
     print(f"[plain] batched {st_b.tolist()} plain {st_p.tolist()} wall {wall:.2f}s", flush=True)
     assert (st_b > 0).all() and (st_p > 0).all()
     assert np.abs(st_b - st_p).max() <= 500
+
+
+def test_batch_mixes_all_schemes_and_laws():
+    groups = [make_wl(5, 3, 3, 13, 'weno5', A=0.9, dt=1e-4),
+              make_wl(5, 4, 3, 11, 'linear5', A=0.5, dt=1e-4),
+              make_wl(4, 2, 1, 10, 'upwind2', pr=1.0, law='lowmach', kn=0.5, u_w=1e-3, dt=2e-3)]
+    sims = [make_solver(wl, 2, 300 + 10 * g)[0] for g, wl in enumerate(groups)]
+    bt = hrlb.Batch(sims, 4, 1)
+    bt.step(4)
+    for g, (wl, s) in enumerate(zip(groups, sims)):
+        F = s.get_state().cpu().numpy()
+        _, plist = make_solver(wl, 2, 300 + 10 * g)
+        for b in range(2):
+            Fo, m, _ = oracle_run(wl, 4, seed=300 + 10 * g + b, params=plist[b])
+            assert_parity(F[b], Fo, m, f"group {g} instance {b}")

@@ -20,6 +20,9 @@ SMALL = [
     ('upwind2-bgk', make_wl(5, 3, 3, 13, 'upwind2', pr=1.0, omega=1.0)),
     ('weno5-sutherland', make_wl(4, 5, 3, 11, 'weno5', law='sutherland', suth_S=0.5239, kn=0.05, u_w=1.0)),
     ('weno5-collisionless', make_wl(6, 4, 2, 9, 'weno5', collisionless=True, u_w=0.5)),
+    ('linear5-shakhov', make_wl(5, 4, 3, 13, 'linear5', A=0.5, dt=1e-4)),
+    ('upwind2-lowmach', make_wl(4, 2, 1, 10, 'upwind2', pr=1.0, law='lowmach', kn=0.5, u_w=1e-5, dt=2e-3)),
+    ('weno5-lowmach', make_wl(7, 2, 1, 12, 'weno5', pr=1.0, law='lowmach', kn=0.05, u_w=1e-3, A=0.98, dt=1e-4)),
 ]
 
 

@@ -102,3 +102,19 @@ def test_collisionless_run_converges_to_free_molecular_solution():
     assert np.allclose(mom.P['xy'], cf['xy'], rtol=1e-9)
     # Pi = -T_xy / (u_w sqrt 2) (Eq. stress) -> 1/sqrt(pi)
     assert np.allclose(-mom.P['xy'] / (u_w * math.sqrt(2)), 1 / math.sqrt(math.pi), rtol=1e-9)
+
+
+def test_lowmach_law_is_constant_and_gives_linear_response():
+    """Sec. IV: at wall speeds ~1e-5 the flow is the linear response of the gas at rest, with
+    tau = k / sqrt(2) (Eq. knLuo) independent of n and T, on HHLB(N_x; Q_x) x HLB(1; 2)."""
+    base = dict(Qx=4, Qy=2, Qz=1, S=8, dt=2e-3, kn=0.5, pr=1.0, law='lowmach', scheme='upwind2')
+    p = sv.Params(u_w=1e-5, **base)
+    tau = sv.relaxation_time(np.array([0.5, 1.0, 2.0]), np.array([0.7, 1.0, 1.9]), p)
+    assert np.all(tau == 0.5 / np.sqrt(2.0))
+    prof = []
+    for u in (1e-5, 2e-5):
+        m = sv.Model(sv.Params(u_w=u, **base))
+        F = sv.run(sv.equilibrium_state(m), m, 400)
+        prof.append(sv.moments(F, m).u[1] / u)
+    assert np.abs(prof[0]).max() > 0.05
+    assert np.abs(prof[0] - prof[1]).max() <= 1e-4 * np.abs(prof[0]).max()
