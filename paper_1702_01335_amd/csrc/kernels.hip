@@ -351,25 +351,42 @@ __device__ __forceinline__ dbl4 moment_mfma(const double* ft, const double* a, i
 // the multipliers of the wave's velocities (A operands loaded here, from the small,
 // cache-resident multiplier table, so they hold no registers during the march), sum over
 // the block's waves and write the block's partials for nodes s .. s+cnt-1.
-// contract the wave tiles of 16 node rows with the moment multipliers (matrix cores) into
-// lds_red[wave][node][16]
-__device__ __forceinline__ void moment_contract(double* lds_ft, double* lds_red, const double* __restrict__ ptab,
-                                                int wave_v0, int V, int wave, int lane) {
+// Moment sums of a group of 16 node rows.  The wave contracts its tile with the
+// multipliers of its 64 velocities on the matrix cores; the 13 sums of node n end up in
+// the lane pair that holds D[.][n].  A block of one wave stores them straight from these
+// registers; with more waves they are added across waves in LDS first.
+__device__ __forceinline__ dbl4 moment_contract(const double* lds_ft, const double* __restrict__ ptab, int wave_v0,
+                                                int V, int wave, int lane) {
   double a[16];
   load_moment_operands(ptab, wave_v0, V, lane, a);
   __syncthreads();
-  const dbl4 acc = moment_mfma(lds_ft + wave * FT_WAVE, a, lane);
+  return moment_mfma(lds_ft + wave * FT_WAVE, a, lane);
+}
+
+// park a wave's contraction in lds_red[wave][node][16] (blocks of several waves)
+__device__ __forceinline__ void park_moments(double* lds_red, const dbl4& acc, int wave, int lane) {
   double* r = lds_red + wave * RED_WAVE + (lane & 15) * 16 + (lane >> 4);
   r[0] = acc[0];
   r[4] = acc[1];
   r[8] = acc[2];
   r[12] = acc[3];
-  __syncthreads();
 }
 
-// sum the waves' contractions of cnt nodes and store them, node-major with node_stride
-__device__ __forceinline__ void store_moments(const double* lds_red, int waves, int cnt, double* __restrict__ out,
-                                              int node_stride) {
+// store the moment sums of cnt nodes, node-major with node_stride: from the registers of a
+// one-wave block (register r of lane l holds moment 4 r + l / 16 of node l % 16), or from
+// the waves' parked contractions summed in LDS
+__device__ __forceinline__ void store_moments(const dbl4& acc, const double* lds_red, int waves, int cnt,
+                                              double* __restrict__ out, int node_stride) {
+  if (waves == 1) {
+    const int lane = threadIdx.x, n = lane & 15, m0 = lane >> 4;
+    if (n < cnt) {
+      double* o = out + (size_t)n * node_stride + m0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (m0 + 4 * r < NMOM) o[4 * r] = acc[r];
+    }
+    return;
+  }
   for (int idx = threadIdx.x; idx < cnt * NMOM; idx += blockDim.x) {
     const int n = idx / NMOM, q = idx - n * NMOM;
     double s = 0.0;
@@ -378,19 +395,17 @@ __device__ __forceinline__ void store_moments(const double* lds_red, int waves, 
   }
 }
 
-__device__ __forceinline__ void flush_group(double* lds_ft, double* lds_red, const double* __restrict__ ptab,
-                                            int wave_v0, int V, int wave, int waves, int lane, int cnt,
-                                            double* __restrict__ out, int node_stride) {
-  moment_contract(lds_ft, lds_red, ptab, wave_v0, V, wave, lane);
-  store_moments(lds_red, waves, cnt, out, node_stride);
-}
+// LDS of the stage and partials kernels (doubles): the waves' node tiles, then (blocks of
+// several waves) the parked contractions, then two residual sums per wave
+__host__ __device__ inline int lds_red_offset(int waves) { return waves * FT_WAVE; }
+__host__ __device__ inline int lds_res_offset(int waves) { return waves * FT_WAVE + (waves > 1 ? waves * RED_WAVE : 0); }
 
 __global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, const double* __restrict__ F, int nvb,
                                                        int nch, int cs) {
   extern __shared__ double lds[];
   const int waves = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double* lds_ft = lds;
-  double* lds_red = lds + waves * FT_WAVE;
+  double* lds_red = lds + lds_red_offset(waves);
   int t = xcd_tile(blockIdx.x, gridDim.x);
   const int ch = t % nch;
   t /= nch;
@@ -409,7 +424,12 @@ __global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, cons
   for (int g = 0; g < nloc; g += 16) {
     const int cnt = min(16, nloc - g);
     for (int u = 0; u < 16; ++u) ft[u * FT_LD + lane] = (u < cnt && active) ? Fb[(size_t)(s0 + g + u) * V + v] : 0.0;
-    flush_group(lds_ft, lds_red, d.ptab, wave_v0, V, wave, waves, lane, cnt, part + (size_t)g * nstride, nstride);
+    const dbl4 acc = moment_contract(lds_ft, d.ptab, wave_v0, V, wave, lane);
+    if (waves > 1) {
+      park_moments(lds_red, acc, wave, lane);
+      __syncthreads();
+    }
+    store_moments(acc, lds_red, waves, cnt, part + (size_t)g * nstride, nstride);
     __syncthreads();
   }
 }
@@ -663,8 +683,8 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
                                            int cs, double* lds) {
   const int waves = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double* lds_ft = lds;
-  double* lds_red = lds + waves * FT_WAVE;
-  double* lds_res = lds_red + waves * RED_WAVE;
+  double* lds_red = lds + lds_red_offset(waves);
+  double* lds_res = lds + lds_res_offset(waves);
   const int S = sh.S, V = sh.V, Qx = sh.Qx;
   const int v = vb * blockDim.x + threadIdx.x;
   const bool active = v < V;
@@ -782,6 +802,7 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   }
 
   int last_cnt = 0, last_g = 0;
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
   for (int g = 0; g < nloc; g += 16) {
     const int cnt = min(16, nloc - g);
     // the 16 nodes of a group as straight-line code (uniform guards for the last, partial
@@ -809,12 +830,16 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
       double* dst = Fout + base + (size_t)(s0 + g) * V + v;
       for (int u = 0; u < cnt; ++u) dst[(size_t)u * V] = ft[u * FT_LD + lane];
     }
-    if (g > 0) store_moments(lds_red, waves, 16, part + (size_t)(g - 16) * nstride, nstride);
-    moment_contract(lds_ft, lds_red, d.ptab, wave_v0, V, wave, lane);
+    if (g > 0) store_moments(acc, lds_red, waves, 16, part + (size_t)(g - 16) * nstride, nstride);
+    acc = moment_contract(lds_ft, d.ptab, wave_v0, V, wave, lane);
+    if (waves > 1) {
+      park_moments(lds_red, acc, wave, lane);
+    }
+    __syncthreads();
     last_cnt = cnt;
     last_g = g;
   }
-  store_moments(lds_red, waves, last_cnt, part + (size_t)last_g * nstride, nstride);
+  store_moments(acc, lds_red, waves, last_cnt, part + (size_t)last_g * nstride, nstride);
   if constexpr (STAGE == 3) {
     rd = wave_sum(rd);
     rf = wave_sum(rf);
@@ -931,7 +956,7 @@ int launch_clear_flags(const Shape& sh, const DevPtrs& d, void* stream) {
   return (int)hipGetLastError();
 }
 
-static size_t stage_lds_bytes(int waves) { return ((size_t)waves * (FT_WAVE + RED_WAVE) + 2 * waves) * sizeof(double); }
+static size_t stage_lds_bytes(int waves) { return ((size_t)lds_res_offset(waves) + 2 * waves) * sizeof(double); }
 
 int launch_partials(const Shape& sh, const DevPtrs& d, const double* F, int cells, int waves, void* stream) {
   int nvb, nch;
