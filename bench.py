@@ -38,6 +38,8 @@ def parse():
     ap.add_argument('--no-cpu', action='store_true')
     ap.add_argument('--eager', action='store_true', help='launch kernels one by one instead of replaying a HIP graph')
     ap.add_argument('--no-tune', action='store_true', help='keep the default launch shape instead of autotuning it')
+    ap.add_argument('--tune-cache', default=os.path.join(ROOT, 'paper_1702_01335_amd', 'tuned_launch.jsonl'),
+                    help='JSON-lines cache of autotuned launch shapes (a shape found there is used without timing)')
     ap.add_argument('--copy-probe-mib', type=int, default=0,
                     help='also run one device copy of this size (calibrates HBM byte counters under a profiler)')
     ap.add_argument('--cpu-seconds', type=float, default=15.0)
@@ -232,8 +234,9 @@ def main():
         solver.set_launch(args.cells or c0, args.waves or w0)
     elif not args.no_tune:
         # the library's autotuner times every (node chunk, waves) shape on this state
-        c_t, w_t, ms_t = solver.autotune(probe_steps=3)
-        tuned = dict(cells=c_t, waves=w_t, probe_ms_per_step=ms_t)
+        c_t, w_t, ms_t = solver.autotune(probe_steps=3, cache_path=args.tune_cache)
+        tuned = dict(cells=c_t, waves=w_t, probe_ms_per_step=ms_t if ms_t >= 0 else None,
+                     source='timed now' if ms_t >= 0 else args.tune_cache)
     cells, waves = solver.get_launch()
     solver.set_graph(not args.eager)
     pairs = args.batch * wl['S'] * q.V
