@@ -454,16 +454,30 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
     const InstDev* in = d.inst + b;
     const int V = sh.V;
     const double* F = Fin + (size_t)b * S * V;
+    double ex[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) ex[q] = in->ex[q];
     double acc = 0.0;
-    for (int v = sh.Qx * sh.QyQz + lane; v < V; v += 64) {
-      const double px = d.px[v / sh.QyQz];
-      const double f3 = F[(size_t)(S - 3) * V + v], f2 = F[(size_t)(S - 2) * V + v], f1 = F[(size_t)(S - 1) * V + v];
-      const double g0 = in->ex[0] * f1 + in->ex[1] * f2 + in->ex[2] * f3;
-      const double g1 = in->ex[3] * g0 + in->ex[4] * f1 + in->ex[5] * f2;
-      const double r = (sh.scheme == 1)   ? weno5(f3, f2, f1, g0, g1)
-                       : (sh.scheme == 2) ? linear5(f3, f2, f1, g0, g1)
-                                          : (1.5 * f1 - 0.5 * f2);
-      acc += px * r;
+    // four velocities per lane and pass, their twelve loads issued before any is used
+    for (int v0 = sh.Qx * sh.QyQz + lane; v0 < V; v0 += 256) {
+      double px[4], f1[4], f2[4], f3[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int v = min(v0 + 64 * k, V - 1);
+        px[k] = (v0 + 64 * k < V) ? d.px[v / sh.QyQz] : 0.0;
+        f3[k] = F[(size_t)(S - 3) * V + v];
+        f2[k] = F[(size_t)(S - 2) * V + v];
+        f1[k] = F[(size_t)(S - 1) * V + v];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double g0 = ex[0] * f1[k] + ex[1] * f2[k] + ex[2] * f3[k];
+        const double g1 = ex[3] * g0 + ex[4] * f1[k] + ex[5] * f2[k];
+        const double r = (sh.scheme == 1)   ? weno5(f3[k], f2[k], f1[k], g0, g1)
+                         : (sh.scheme == 2) ? linear5(f3[k], f2[k], f1[k], g0, g1)
+                                            : (1.5 * f1[k] - 0.5 * f2[k]);
+        acc += px[k] * r;
+      }
     }
     acc = wave_sum(acc);
     if (lane == 0) {
@@ -478,36 +492,63 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
   const int nphx = sh.Qx * (sh.Nx + 1), nphy = sh.Qy * (sh.Ny + 1), nphz = sh.Qz * (sh.Nz + 1);
   const int oJm = sh.Nx + 1, oay = 2 * (sh.Nx + 1), oaz = oay + sh.Ny + 1, SC = oaz + sh.Nz + 1;
   const int Qyz = sh.Qy + sh.Qz;
+  const int ncx = (sh.Nx + 1) * (sh.Nx + 1);
   double* msum = cl_lds;
   double* scal = msum + nb * PART_STRIDE;
   double* phix = scal + nb * SC;
   double* phiy = phix + nphx;
   double* phiz = phiy + nphy;
   double* gyz = phiz + nphz;
+  double* cxl = gyz + nb * Qyz;
   const int total = sh.B * S;
   const int g0 = blk * nb;
   const int nblk_nodes = min(nb, total - g0);
-  for (int e = lane; e < nphx; e += 64) phix[e] = d.phix[e];
-  for (int e = lane; e < nphy; e += 64) phiy[e] = d.phiy[e];
-  for (int e = lane; e < nphz; e += 64) phiz[e] = d.phiz[e];
-  // 1) sum the moment partials over velocity blocks.  They are node-major ([node][nvb][16]),
-  //    so the block's nodes are one contiguous range; a thread owns (node, moment) pairs
-  //    and sums their nvb entries with four independent accumulators in flight
-  for (int e = lane; e < nblk_nodes * PART_STRIDE; e += 64) {
-    const int nd = e >> 4, q = e & 15;
-    const double* src = d.partials + (size_t)(g0 + nd) * nvb * PART_STRIDE + q;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    if (q < NMOM) {
-      int vb = 0;
-      for (; vb + 3 < nvb; vb += 4) {
-        a0 += src[(size_t)vb * PART_STRIDE];
-        a1 += src[(size_t)(vb + 1) * PART_STRIDE];
-        a2 += src[(size_t)(vb + 2) * PART_STRIDE];
-        a3 += src[(size_t)(vb + 3) * PART_STRIDE];
+  // Every load of a phase is issued before any of its results is used: the block's time
+  // is a chain of memory round trips, so each phase should cost one.
+  // 0) the projection tables (and the half-range monomial coefficients) into LDS
+  {
+    const int n1 = nphx, n2 = n1 + nphy, n3 = n2 + nphz, n4 = n3 + ncx;
+    for (int e0 = lane; e0 < n4; e0 += 256) {
+      double x[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = e0 + 64 * k;
+        x[k] = (e < n1) ? d.phix[e] : (e < n2) ? d.phiy[e - n1] : (e < n3) ? d.phiz[e - n2] : (e < n4) ? d.cx[e - n3] : 0.0;
       }
-      for (; vb < nvb; ++vb) a0 += src[(size_t)vb * PART_STRIDE];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = e0 + 64 * k;
+        if (e < n3) phix[e] = x[k];  // phix, phiy, phiz are contiguous in LDS
+        else if (e < n4) cxl[e - n3] = x[k];
+      }
     }
-    msum[e] = (a0 + a1) + (a2 + a3);
+  }
+  // 1) sum the moment partials over velocity blocks.  They are node-major ([node][nvb][16]),
+  //    so the block's nodes are one contiguous range; lane l owns moment l % 16 of nodes
+  //    l / 16 + 4 j and sums four velocity blocks per pass for all of them at once
+  {
+    const int q = lane & 15, n0 = lane >> 4;
+    for (int j0 = 0; j0 < nb; j0 += 16) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int vb0 = 0; vb0 < nvb; vb0 += 4) {
+        double x[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int nd = j0 + n0 + 4 * j;
+          const bool ok = nd < nblk_nodes && q < NMOM;
+          const double* src = d.partials + ((size_t)(g0 + (ok ? nd : 0)) * nvb) * PART_STRIDE + q;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) x[j][t] = (ok && vb0 + t < nvb) ? src[(size_t)(vb0 + t) * PART_STRIDE] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] += (x[j][0] + x[j][1]) + (x[j][2] + x[j][3]);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int nd = j0 + n0 + 4 * j;
+        if (nd < nb) msum[nd * PART_STRIDE + q] = acc[j];
+      }
+    }
   }
   __syncthreads();
   // 2) one lane per node: moments, tau, Shakhov coefficients, projection coefficients
@@ -574,12 +615,12 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
     double I[NX_MAX + 1], J[NX_MAX + 1], a[NYZ_MAX + 1];
     const double Tc = bad ? 1.0 : T;
     half_gauss_moments(ux, Tc, I);
-    half_projection(d.cx, sh.Nx, I, J);
+    half_projection(cxl, sh.Nx, I, J);
 #pragma unroll
     for (int l = 0; l <= NX_MAX; ++l)
       if (l <= sh.Nx) sc[l] = n * J[l];
     half_gauss_moments(-ux, Tc, I);
-    half_projection(d.cx, sh.Nx, I, J);
+    half_projection(cxl, sh.Nx, I, J);
 #pragma unroll
     for (int l = 0; l <= NX_MAX; ++l)
       if (l <= sh.Nx) sc[oJm + l] = n * J[l];
@@ -625,7 +666,8 @@ __global__ void __launch_bounds__(64) closure_kernel(Shape sh, DevPtrs d, const 
 // doubles of closure LDS for nb nodes per block
 static inline size_t closure_lds_doubles(const Shape& sh, int nb) {
   return (size_t)nb * PART_STRIDE + (size_t)nb * (2 * (sh.Nx + 1) + sh.Ny + sh.Nz + 2) + (size_t)sh.Qx * (sh.Nx + 1) +
-         (size_t)sh.Qy * (sh.Ny + 1) + (size_t)sh.Qz * (sh.Nz + 1) + (size_t)nb * (sh.Qy + sh.Qz);
+         (size_t)sh.Qy * (sh.Ny + 1) + (size_t)sh.Qz * (sh.Nz + 1) + (size_t)nb * (sh.Qy + sh.Qz) +
+         (size_t)(sh.Nx + 1) * (sh.Nx + 1);
 }
 
 // nodes per closure block: up to 64, fewer when there are few nodes, so the grid keeps
