@@ -47,6 +47,7 @@ def parse():
     ap.add_argument('--sweep-instances', type=int, default=256)
     ap.add_argument('--steady-instances', type=int, default=16)
     ap.add_argument('--no-warm', action='store_true', help='skip the learned warm-start measurement')
+    ap.add_argument('--no-workloads', action='store_true', help='skip the per-workload table')
     ap.add_argument('--warm-train', type=int, default=1000, help='instances whose steady states train the network')
     ap.add_argument('--warm-heldout', type=int, default=100)
     ap.add_argument('--warm-steps', type=int, default=10000, help='AdamW steps of the network')
@@ -168,6 +169,30 @@ def sweep_section(n_inst, n_steady, steps):
                              steps_max=int(st_b.max()), steps_median=float(np.median(st_b)),
                              steps_equal=bool(np.array_equal(st_b, st_p)),
                              max_residual=float(max(R_b.max(), R_p.max())))
+    return out
+
+
+def workloads_section(steps, warmup):
+    """Every workload at its own size: one instance (latency-bound: 0.5 to 118 MB per step)
+    and a batch large enough to live in HBM rather than in the 256 MB last-level cache.
+    Launch shapes autotuned, HIP graph on."""
+    import torch
+    from paper_1702_01335_amd.workloads import workload
+    out = []
+    for name, batch in (('couette_bgk_s64_v128', 1), ('couette_bgk_s64_v128', 4096),
+                        ('couette_shakhov_s256_v800', 1), ('couette_shakhov_s256_v800', 512),
+                        ('couette_shakhov_s512_v3600', 1), ('couette_shakhov_s512_v3600', 64)):
+        wl = workload(name)
+        q, s = make_solver(wl, batch, 'cuda:0')
+        c, w, _ = s.autotune(probe_steps=3)
+        s.set_graph(True)
+        ms, _ = time_steps(s, steps, warmup)
+        pairs = batch * wl['S'] * q.V
+        out.append(dict(workload=name, batch=batch, pairs=pairs, launch=dict(cells=c, waves=w), ms_per_step=ms,
+                        value=pairs / (ms * 1e-3) / 1e9,
+                        hbm_frac_step=pairs * BYTES_PER_PAIR_STEP / (ms * 1e-3) / HBM_PEAK))
+        del s
+        torch.cuda.empty_cache()
     return out
 
 
@@ -301,9 +326,12 @@ def main():
         'wall_s_timed': wall,
     }
     progress(f"step: {value:.2f} G pair-updates/s, stage kernel {stage_avg_s * 1e6:.1f} us")
-    if not args.no_sweep or not args.no_warm:
+    if not args.no_sweep or not args.no_warm or not args.no_workloads:
         del solver
         torch.cuda.empty_cache()
+    if not args.no_workloads:
+        out['workloads'] = workloads_section(min(args.steps, 30), min(args.warmup, 5))
+        progress('workloads: ' + ', '.join(f"{w['workload']} x{w['batch']} {w['value']:.2f}" for w in out['workloads']))
     if not args.no_sweep:
         out['sweep'] = sweep_section(args.sweep_instances, args.steady_instances, min(args.steps, 50))
         progress(f"sweep: {out['sweep']['value']:.2f} G pair-updates/s batched")
