@@ -97,7 +97,9 @@ int hrlb_quad_nodes(const hrlb_quad* q, int axis, double* nodes, double* weights
  *   *state_bytes: three population arrays [batch][S][V] (the step's F_l and two RK
  *                 stage buffers); *work_bytes: tables, moment partials, per-node closure,
  *                 wall densities, residual partials and fault flags.
- * Both buffers must be 256-byte aligned (torch allocations are).
+ * Both buffers must be 256-byte aligned (torch allocations are).  One instance's
+ * populations, S * V * 8 bytes, must stay below 4 GiB (HRLB_EINVAL otherwise); the
+ * batch as a whole has no such limit.
  */
 int hrlb_state_bytes(const hrlb_quad* q, int S, int batch, size_t* state_bytes, size_t* work_bytes);
 
@@ -113,7 +115,8 @@ int hrlb_state_bytes(const hrlb_quad* q, int S, int batch, size_t* state_bytes, 
  *     library's reading.)
  * The quadrature handle must outlive the sim.
  * Errors: HRLB_EINVAL (S < 3, batch < 1, dt <= 0, kn <= 0, T_w <= 0, n0 <= 0, pr <= 0,
- *   A outside [0, 1), unknown law or scheme), HRLB_ENOMEM (buffers too small), HRLB_EHIP.
+ *   A outside [0, 1), unknown law or scheme, one instance's S * V * 8 bytes not below
+ *   4 GiB), HRLB_ENOMEM (buffers too small), HRLB_EHIP.
  */
 int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* params, int batch,
                     void* d_state, size_t state_bytes, void* d_work, size_t work_bytes, void* stream,

@@ -142,6 +142,13 @@ static Shape make_shape(const QuadTables& t, int S, int B, int scheme) {
   return sh;
 }
 
+// The stage kernel addresses one instance's populations and closure records with 32-bit
+// byte offsets.
+static bool instance_fits(const Shape& sh) {
+  const size_t lim = (size_t)1 << 32;
+  return (size_t)sh.S * sh.V * sizeof(double) < lim && (size_t)sh.S * sh.rec_len * sizeof(double) < lim;
+}
+
 // Node positions of App. A.2 (Eqs. stretch, etas), 1-based fractional index s.
 static double node_x(double s, int S, double A) {
   if (A == 0.0) return (s - 0.5) / (2.0 * S);
@@ -222,6 +229,7 @@ int hrlb_state_bytes(const hrlb_quad* q, int S, int batch, size_t* state_bytes, 
   if (!q || !state_bytes || !work_bytes) return fail(HRLB_EINVAL, "state_bytes: NULL argument");
   if (S < 3 || batch < 1) return fail(HRLB_EINVAL, "state_bytes: need S >= 3 and batch >= 1");
   const Shape sh = make_shape(q->t, S, batch, 0);
+  if (!instance_fits(sh)) return fail(HRLB_EINVAL, "state_bytes: one instance's populations (S * V * 8 bytes) must stay below 4 GiB");
   *state_bytes = 3 * align256((size_t)batch * S * sh.V * sizeof(double));
   *work_bytes = work_layout(sh).total;
   return HRLB_OK;
@@ -254,6 +262,7 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
     if (!std::isfinite(p.u_w) || !std::isfinite(p.omega)) return fail(HRLB_EINVAL, "init_state: non-finite u_w/omega" + at);
   }
   const Shape sh = make_shape(q->t, S, batch, scheme);
+  if (!instance_fits(sh)) return fail(HRLB_EINVAL, "init_state: one instance's populations (S * V * 8 bytes) must stay below 4 GiB");
   const WorkLayout L = work_layout(sh);
   const size_t arr = align256((size_t)batch * S * sh.V * sizeof(double));
   if (state_bytes < 3 * arr) return fail(HRLB_ENOMEM, "init_state: state buffer smaller than hrlb_state_bytes");

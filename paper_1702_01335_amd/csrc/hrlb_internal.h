@@ -36,7 +36,7 @@ struct InstDev {
   double dt, kn, omega, suth, pr, n0, T_w, u_w;
   double wall_den;   // sum_{p_x<0} p_x F^eq_w / n_w   (filled on the device)
   double ex[6];      // Lagrange weights: ghost S from S-1,S-2,S-3 and ghost S+1 from S,S-1,S-2 (0-based)
-  double law;        // 0 power, 1 Sutherland
+  double law;        // 0 power, 1 Sutherland, 2 low Mach
   double collisionless;
   double pad;
 };

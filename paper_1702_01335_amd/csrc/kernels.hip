@@ -54,42 +54,42 @@ __device__ __forceinline__ double wave_sum(double x) {
 
 // WENO-5 reconstruction at the interface downstream of c from the upwind-ordered
 // stencil (a, b, c, d, e) (App. A.3; candidates of Eq. weno5_flux, indicators of
-// Eq. weno_sigma, weights of Eq. weno5_omega without epsilon).  The weights
-// (d_q / s_q^2) / sum_r (d_r / s_r^2) are evaluated as N_q / sum N with
-// N_q = d_q prod_{r != q} t_r^2 and t_q = s_q / 2^e, 2^e the binade of max s: one
-// division, exact power-of-two scaling (so the scheme stays homogeneous of degree one),
-// and vanishing indicators give the Table II rows directly (one vanishing: N_q alone
-// survives; two: the sum vanishes and the pair row is taken; three: ideal weights).
+// Eq. weno_sigma, weights of Eq. weno5_omega without epsilon).  The candidates are carried
+// as 6 f_q and the indicators as 12 s_q, so every coefficient is a small integer; the
+// weights (d_q / s_q^2) / sum_r (d_r / s_r^2) do not change under a common factor of the
+// indicators.  They are evaluated as N_q / sum N with N_q = d_q prod_{r != q} t_r^2, the
+// ideal weights d as 1 : 6 : 3 and t_q = s_q / 2^e, 2^e the binade of max s: one division,
+// exact power-of-two scaling (so the scheme stays homogeneous of degree one), and vanishing
+// indicators give the Table II rows directly (one vanishing: N_q alone survives; two: the
+// sum vanishes and the pair row is taken; three: ideal weights).
 __device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
-  const double f1 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
-  const double f2 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
-  const double f3 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
+  const double f1 = 2.0 * a - 7.0 * b + 11.0 * c;
+  const double f2 = -b + 5.0 * c + 2.0 * d;
+  const double f3 = 2.0 * c + 5.0 * d - e;
   const double r1 = a - 2.0 * b + c, q1 = a - 4.0 * b + 3.0 * c;
   const double r2 = b - 2.0 * c + d, q2 = b - d;
   const double r3 = c - 2.0 * d + e, q3 = 3.0 * c - 4.0 * d + e;
-  const double s1 = (13.0 / 12.0) * r1 * r1 + 0.25 * q1 * q1;
-  const double s2 = (13.0 / 12.0) * r2 * r2 + 0.25 * q2 * q2;
-  const double s3 = (13.0 / 12.0) * r3 * r3 + 0.25 * q3 * q3;
+  const double s1 = 13.0 * r1 * r1 + 3.0 * q1 * q1;
+  const double s2 = 13.0 * r2 * r2 + 3.0 * q2 * q2;
+  const double s3 = 13.0 * r3 * r3 + 3.0 * q3 * q3;
   const double smax = fmax(s1, fmax(s2, s3));
-  if (smax == 0.0) return 0.1 * f1 + 0.6 * f2 + 0.3 * f3;
+  if (smax == 0.0) return (f1 + 6.0 * f2 + 3.0 * f3) * (1.0 / 60.0);
   int ex;
   (void)frexp(smax, &ex);
   const double t1 = ldexp(s1, -ex), t2 = ldexp(s2, -ex), t3 = ldexp(s3, -ex);
   const double u1 = t1 * t1, u2 = t2 * t2, u3 = t3 * t3;
-  const double n1 = 0.1 * (u2 * u3), n2 = 0.6 * (u1 * u3), n3 = 0.3 * (u1 * u2);
+  const double n1 = u2 * u3, n2 = 6.0 * (u1 * u3), n3 = 3.0 * (u1 * u2);
   const double den = n1 + n2 + n3;
-  if (den > 0.0) return (n1 * f1 + n2 * f2 + n3 * f3) / den;
-  if (u1 == 0.0 && u2 == 0.0) return (1.0 / 7.0) * f1 + (6.0 / 7.0) * f2;
-  if (u1 == 0.0 && u3 == 0.0) return 0.25 * f1 + 0.75 * f3;
-  return (2.0 / 3.0) * f2 + (1.0 / 3.0) * f3;
+  if (den > 0.0) return (n1 * f1 + n2 * f2 + n3 * f3) / (6.0 * den);
+  if (u1 == 0.0 && u2 == 0.0) return (f1 + 6.0 * f2) * (1.0 / 42.0);
+  if (u1 == 0.0 && u3 == 0.0) return (f1 + 3.0 * f3) * (1.0 / 24.0);
+  return (2.0 * f2 + f3) * (1.0 / 18.0);
 }
 
-// the WENO-5 candidates with the ideal weights: the linear fifth-order upwind flux
+// the WENO-5 candidates with the ideal weights: the linear fifth-order upwind flux,
+// (0.1 f1 + 0.6 f2 + 0.3 f3) with the candidates expanded
 __device__ __forceinline__ double linear5(double a, double b, double c, double d, double e) {
-  const double f1 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
-  const double f2 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
-  const double f3 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
-  return 0.1 * f1 + 0.6 * f2 + 0.3 * f3;
+  return (2.0 * a - 13.0 * b + 47.0 * c + 27.0 * d - 3.0 * e) * (1.0 / 60.0);
 }
 
 template <int SCHEME>
@@ -603,14 +603,13 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
     rec[0] = ux;
     rec[1] = uy;
     rec[2] = uz;
-    rec[3] = invtau;
+    rec[3] = in->dt * invtau;
     rec[4] = Cs;
     rec[5] = Cs / (5.0 * T);
     rec[6] = qx;
     rec[7] = qy;
     rec[8] = qz;
-    rec[9] = n;
-    rec[10] = T;
+    rec[9] = in->dt * d.inv_dx[g];
     // projection coefficients of the 1D Maxwellian factors (Sec. III)
     double I[NX_MAX + 1], J[NX_MAX + 1], a[NYZ_MAX + 1];
     const double Tc = bad ? 1.0 : T;
@@ -695,14 +694,29 @@ __device__ __forceinline__ double raw_node(const double* __restrict__ Fb, int c,
   return Fb[(size_t)node * V + vel];
 }
 
+// buffer resource over an instance's array (raw, unbounded: every offset the kernels form is
+// clamped into the array) and a load at a wave-uniform byte offset (scalar register) plus a
+// fixed per-lane byte offset; both offsets are 32-bit, which holds because the host keeps
+// one instance's state below 4 GiB
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const double* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0, -1, 0x00020000);
+}
+
+__device__ __forceinline__ double ld_buf(__amdgpu_buffer_rsrc_t r, unsigned lane_off, unsigned row_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, row_off, 0));
+}
+
 // complete a node beyond the wall (App. A.4): p_x > 0 by quadratic extrapolation from the
 // three nodes below (f1 nearest), p_x < 0 the wall Maxwellian n_w F^eq_w; nodes past
-// the third ghost are never read
+// the third ghost are never read.  The extrapolation weights (uniform) are read by scalar
+// loads on the ghost path only, so they hold no registers on the interior march.
 __device__ __forceinline__ double ghost_node(double raw, int c, int S, bool pos, double f1, double f2, double f3,
                                              const double* ex, double ghost_in) {
+  typedef __attribute__((address_space(4))) const double cdouble;
   if (c < S) return raw;
-  if (c == S) return pos ? ex[0] * f1 + ex[1] * f2 + ex[2] * f3 : ghost_in;
-  if (c == S + 1) return pos ? ex[3] * f1 + ex[4] * f2 + ex[5] * f3 : ghost_in;
+  const cdouble* e = (const cdouble*)ex;
+  if (c == S) return pos ? e[0] * f1 + e[1] * f2 + e[2] * f3 : ghost_in;
+  if (c == S + 1) return pos ? e[3] * f1 + e[4] * f2 + e[5] * f3 : ghost_in;
   return pos ? 0.0 : ghost_in;
 }
 
@@ -738,15 +752,11 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   const size_t base = (size_t)b * S * V;
   const double* Fb = Fin + base;
   const InstDev* in = d.inst + b;
-  const double dt = in->dt;
-  double ex[6];
-#pragma unroll
-  for (int q = 0; q < 6; ++q) ex[q] = in->ex[q];
+  const double* ex = in->ex;
   const double ghost_in = active ? d.nw[b] * d.g_wall[(size_t)b * V + vv] : 0.0;
   const int wave_v0 = vb * blockDim.x + wave * 64;
   const int s0 = ch * cs;
   const int nloc = min(cs, S - s0);
-  const double* invdx = d.inv_dx + (size_t)b * S;
   const double* recb = d.rec + (size_t)b * S * sh.rec_len;
   double* ft = lds_ft + wave * FT_WAVE;
   // partials are node-major, [b][S][nvb][16]
@@ -767,38 +777,50 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
 
   // Per-node operands, software-pipelined in rotating register sets (the node loop is
   // unrolled by PIPE, so no register with a load in flight is ever copied).  The two HBM
-  // streams, the window node c+3 and F_l, run PIPE nodes ahead; the gathers that hit the
-  // cache (the two equilibrium factors and the node's uniform closure scalars: lane q < 9
-  // loads record field q -- u, 1/tau, Shakhov coefficients, q -- and lane 9 loads 1/dx,
-  // broadcast with readlane where used) run two nodes ahead.  All are unconditional
-  // vector loads with clamped addresses, which complete in order.
+  // streams, the window node c+3 and F_l, and the gathers that hit the cache (the two
+  // equilibrium factors and the node's uniform closure scalars: lane q < 10 loads record
+  // field q -- u, 1/tau, Shakhov coefficients, q, 1/dx -- broadcast with readlane where
+  // used) run PIPE nodes ahead.  All are unconditional vector loads with clamped addresses,
+  // which complete in order; each is a wave-uniform row address plus a fixed 32-bit lane
+  // offset, so no address arithmetic is repeated per lane and node.
   struct Far {
     double raw, fl0;
   };
   struct Near {
-    double gx, gyz, sc;
+    double gx, gyz;
   };
+  // the node's closure scalars (record head: u, dt / tau, the two Shakhov coefficients, q,
+  // dt / dx), wave-uniform, read by scalar loads
+  struct Sc {
+    double ux, uy, uz, itau, cs, a, qx, qy, qz, idx;
+  };
+  typedef __attribute__((address_space(4))) const double cdouble;
   const int clast = s0 + nloc - 1;
   const int gx_off = REC_HEAD + i, gyz_off = REC_HEAD + 2 * Qx + jk;
-  const int sq = lane < 9 ? lane : 0;
+  const unsigned vv8 = 8u * vv, gx8 = 8u * gx_off, gyz8 = 8u * gyz_off;
+  const __amdgpu_buffer_rsrc_t r_in = raw_rsrc(Fb), r_rec = raw_rsrc(recb);
+  const __amdgpu_buffer_rsrc_t r_l = raw_rsrc(STAGE != 1 ? Fl + base : Fb);
+  const unsigned row8 = 8u * V, rec8 = 8u * sh.rec_len;
   auto ld_far = [&](int c, Far& o) {
-    o.raw = raw_node(Fb, c + 3, S, V, vv, vm);
+    // c + 3 >= 3 on the march: never a bounce-back image
+    o.raw = ld_buf(r_in, vv8, row8 * min(c + 3, S - 1));
     if constexpr (STAGE != 1)
-      o.fl0 = Fl[base + (size_t)min(c, clast) * V + vv];
+      o.fl0 = ld_buf(r_l, vv8, row8 * min(c, clast));
     else
       o.fl0 = 0.0;
   };
   auto ld_near = [&](int c, Near& o) {
-    const int cc = min(c, clast);
-    const double* rec = recb + (size_t)cc * sh.rec_len;
-    o.gx = rec[gx_off];
-    o.gyz = rec[gyz_off];
-    const double* sp = (lane == 9) ? invdx + cc : rec + sq;
-    o.sc = *sp;
+    const unsigned ro = rec8 * min(c, clast);
+    o.gx = ld_buf(r_rec, gx8, ro);
+    o.gyz = ld_buf(r_rec, gyz8, ro);
+  };
+  auto ld_sc = [&](int c, Sc& o) {
+    cdouble* r = (cdouble*)(recb + (size_t)min(c, clast) * sh.rec_len);
+    o = Sc{r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], r[8], r[9]};
   };
   double rd = 0.0, rf = 0.0;
   // one node: complete the window, flux, collision, RK combine, store; returns F_out
-  auto node = [&](int c, const Far& o, const Near& p) -> double {
+  auto node = [&](int c, const Far& o, const Near& p, const Sc& z, bool valid) -> double {
     const double Wn = ghost_node(o.raw, c + 3, S, pos, W5, W4, W3, ex, ghost_in);
     W0 = W1;
     W1 = W2;
@@ -806,55 +828,66 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
     W3 = W4;
     W4 = W5;
     W5 = Wn;
-    const double scc = p.sc;
     const double fr = stencil_flux<SCHEME>(pos, px, W0, W1, W2, W3, W4, W5);
-    const double D = (fr - fl) * bcast(scc, 9);  // Eq. flux
+    const double D = (fr - fl) * z.idx;  // dt times Eq. flux
     fl = fr;
     const double F = W2;
     const double feq = p.gx * p.gyz;
-    const double Cs = bcast(scc, 4);
     double FS = feq;
-    if (Cs != 0.0) {
-      const double xx = px - bcast(scc, 0), xy = py - bcast(scc, 1), xz = pz - bcast(scc, 2);
+    if (z.cs != 0.0) {
+      const double xx = px - z.ux, xy = py - z.uy, xz = pz - z.uz;
       const double xi2 = xx * xx + xy * xy + xz * xz;
-      const double qxi = bcast(scc, 6) * xx + bcast(scc, 7) * xy + bcast(scc, 8) * xz;
-      FS = feq + feq * ((bcast(scc, 5) * xi2 - Cs) * qxi);  // F^eq (1 + S), Eq. sdef
+      const double qxi = z.qx * xx + z.qy * xy + z.qz * xz;
+      FS = feq + feq * ((z.a * xi2 - z.cs) * qxi);  // F^eq (1 + S), Eq. sdef
     }
-    const double G = F + dt * ((FS - F) * bcast(scc, 3) - D);  // F + dt L[F], Eq. L_def
+    const double G = F + (FS - F) * z.itau - D;  // F + dt L[F], Eq. L_def
     double out;
     if constexpr (STAGE == 1) {
       out = G;
     } else if constexpr (STAGE == 2) {
       out = 0.75 * o.fl0 + 0.25 * G;
     } else {
-      out = (1.0 / 3.0) * o.fl0 + (2.0 / 3.0) * G;
-      const double dlt = active ? out - o.fl0 : 0.0;
-      const double flm = active ? o.fl0 : 0.0;
-      rd += dlt * dlt;
+      // F_{l+1} = F_l / 3 + 2 G / 3, with the step's change F_{l+1} - F_l formed directly;
+      // the residual sums take active lanes of the chunk's nodes only (vf is uniform)
+      const double dlt = (2.0 / 3.0) * (G - o.fl0);
+      out = o.fl0 + dlt;
+      const double vf = valid ? 1.0 : 0.0;
+      const double dm = active ? dlt * vf : 0.0;
+      const double flm = active ? o.fl0 * vf : 0.0;
+      rd += dm * dm;
       rf += flm * flm;
+      // keep each node's update here: sunk to the end of the 16-node group, the updates
+      // would hold every node's terms live and cost a wave per SIMD of occupancy
+      asm volatile("" : "+v"(rd), "+v"(rf));
     }
+    // nodes past the chunk's end give finite values (clamped loads) that are neither
+    // stored nor summed
     return active ? out : 0.0;
   };
   Far far[PIPE];
   Near near[PIPE];
+  Sc sc[2];
 #pragma unroll
   for (int k = 0; k < PIPE; ++k) {
     ld_far(s0 + k, far[k]);
     ld_near(s0 + k, near[k]);
   }
+  ld_sc(s0, sc[0]);
 
   int last_cnt = 0, last_g = 0;
   dbl4 acc = {0.0, 0.0, 0.0, 0.0};
   for (int g = 0; g < nloc; g += 16) {
     const int cnt = min(16, nloc - g);
-    // the 16 nodes of a group as straight-line code (uniform guards for the last, partial
-    // group): the load counter's state is then known exactly at every wait, which a loop
-    // back-edge inside the group would blur into a full drain
+    // the 16 nodes of a group as straight-line code: the load counter's state is then known
+    // exactly at every wait, which a loop back-edge inside the group would blur into a full
+    // drain.  The nodes past the chunk's end in a last, partial group are computed too, from
+    // clamped (valid) addresses, and give zero: a guard around them would merge the sliding
+    // window at every node and cost a register copy per window entry.
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int c = s0 + g + u;
-      double out = 0.0;
-      if (u < cnt) out = node(c, far[u % PIPE], near[u % PIPE]);
+      ld_sc(c, sc[0]);
+      const double out = node(c, far[u % PIPE], near[u % PIPE], sc[0], u < cnt);
       ft[u * FT_LD + lane] = out;
       // the prefetches are issued on every path (clamped addresses): a load under a branch
       // would have to be merged into one register at the join, and that copy would wait
@@ -898,8 +931,9 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   }
 }
 
+// the stage kernels are held to three waves per SIMD (at most 168 VGPRs)
 template <int SCHEME, int STAGE>
-__global__ void __launch_bounds__(256) stage_kernel(Shape sh, DevPtrs d, const double* __restrict__ Fin,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) stage_kernel(Shape sh, DevPtrs d, const double* __restrict__ Fin,
                                                     const double* Fl, double* Fout, int nvb, int nch, int cs) {
   extern __shared__ double lds[];
   int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -912,7 +946,7 @@ __global__ void __launch_bounds__(256) stage_kernel(Shape sh, DevPtrs d, const d
 // batched (ragged) launches: one persistent grid serves the tiles of every group
 
 template <int STAGE>
-__global__ void __launch_bounds__(256) batch_stage_kernel(const GroupDesc* __restrict__ groups,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) batch_stage_kernel(const GroupDesc* __restrict__ groups,
                                                           const int4* __restrict__ tiles, const int* __restrict__ ntiles) {
   extern __shared__ double lds[];
   const int n = *ntiles;

@@ -156,3 +156,59 @@ class Sweep:
             wall += time.perf_counter() - t0
             del s
         return steps, R, wall
+
+
+def main():
+    """Run a sampled sweep to steady state as one batch and report the per-instance steps.
+    The one-instance-at-a-time time is estimated from each instance's step count and the
+    measured step time of one instance of its shape (HIP graph, autotuned launch)."""
+    import argparse
+    import json
+
+    import torch
+
+    ap = argparse.ArgumentParser(description=main.__doc__.split('\n')[0])
+    ap.add_argument('--instances', type=int, default=256)
+    ap.add_argument('--seed', type=int, default=20170204)
+    ap.add_argument('--tol', type=float, default=1e-10)
+    ap.add_argument('--max-steps', type=int, default=2000000)
+    ap.add_argument('--check-every', type=int, default=1000)
+    ap.add_argument('--out', default=None)
+    a = ap.parse_args()
+    sw = Sweep(sample(a.instances, a.seed))
+    c, w, _ = sw.autotune(probe_steps=3)
+    print(json.dumps({'groups': [[k[0], k[1], len(i)] for k, i, _ in sw.groups], 'launch': [c, w]}), flush=True)
+    steps, R, wall = sw.run_to_steady(a.tol, a.max_steps, a.check_every)
+    print(json.dumps({'batched_wall_s': wall, 'converged': int((steps > 0).sum())}), flush=True)
+    # single-instance step time per shape
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_shape = {}
+    for key, idx, _ in sw.groups:
+        s = sw._solver(key, [idx[0]])
+        s.autotune(probe_steps=3)
+        s.set_graph(True)
+        s.step(5)
+        e0.record()
+        s.step(50)
+        e1.record()
+        e1.synchronize()
+        t_shape[key] = e0.elapsed_time(e1) / 50 / 1e3
+        del s
+    plain = 0.0
+    for k, i in enumerate(sw.order):
+        d = sw.instances[i]
+        n = steps[k] if steps[k] > 0 else a.max_steps
+        plain += n * t_shape[(d['Qx'], d['S'])]
+    res = dict(instances=a.instances, seed=a.seed, tol=a.tol, check_every=a.check_every, launch=[c, w],
+               converged=int((steps > 0).sum()), batched_wall_s=wall, plain_estimate_s=plain,
+               speedup_estimate=plain / wall, steps_max=int(steps.max()), steps_median=float(np.median(steps)),
+               single_step_ms={f"Qx{k[0]}_S{k[1]}": v * 1e3 for k, v in t_shape.items()},
+               steps=[int(x) for x in steps], max_residual=float(R.max()))
+    print(json.dumps({k: v for k, v in res.items() if k != 'steps'}), flush=True)
+    if a.out:
+        with open(a.out, 'w') as f:
+            json.dump(res, f, indent=1)
+
+
+if __name__ == '__main__':
+    main()
