@@ -144,3 +144,20 @@ def test_mlp_sizes_and_argument_checks():
     assert lib.hrlb_mlp_forward(None, fake, 4, fake) == hrlb.HRLB_EINVAL
     assert lib.hrlb_mlp_train_step(None, fake, fake, None, 4, 1e-3, 0.0, None) == hrlb.HRLB_EINVAL
     assert lib.hrlb_seed_state(None, fake, 1, None) == hrlb.HRLB_EINVAL
+
+
+def test_instance_of_four_gib_is_rejected():
+    """One instance's populations are addressed with 32-bit byte offsets: S V 8 must stay
+    below 4 GiB (V = 2 * 128 * 16 * 16 = 65536 here, so the limit falls at S = 8192)."""
+    q = hrlb.Quadrature(128, 16, 16)
+    assert q.V == 65536
+    sb, _ = hrlb.state_bytes(q.handle, 8191, 1)
+    assert sb >= 3 * 8191 * 65536 * 8
+    with pytest.raises(hrlb.HrlbError) as e:
+        hrlb.state_bytes(q.handle, 8192, 1)
+    assert e.value.code == hrlb.HRLB_EINVAL
+    p = hrlb.make_params(kn=0.1, dt=1e-3)
+    with pytest.raises(hrlb.HrlbError) as e:
+        hrlb.init_state(q.handle, 8192, 0, [p], FakeBuf(1 << 20, 1 << 45), FakeBuf(1 << 30, 1 << 40), 0)
+    assert e.value.code == hrlb.HRLB_EINVAL
+    assert '4 GiB' in str(e.value)
