@@ -79,6 +79,7 @@ struct hrlb_batch {
   int* d_items;      // int2 per closure item
   int* d_nitems;
   int max_tiles, max_items, ntiles, nitems;
+  int nb;            // nodes per closure block (all groups)
   int grid_stage, grid_closure;
   size_t lds_stage, lds_closure;
   std::vector<int> active;
@@ -583,13 +584,40 @@ int hrlb_autotune(hrlb_sim* s, int probe_steps, const char* cache_path, int* bes
 
 // ---- batches of sims (ragged sweeps) ---------------------------------------------------
 
-static void batch_sizes(hrlb_sim* const* sims, int nsims, int cells, int waves, int* max_tiles, int* max_items) {
+static int device_cus() {
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    ncu = 256;
+  return ncu;
+}
+
+// Nodes per closure block of a batch, one count for all its groups: the smallest of
+// 4, 8, ..., 64 for which every closure item of the batch (the node blocks of each group
+// plus one wall item per instance) is resident at once, so the closure launch runs in a
+// single round (its time is then one block's critical path, and fewer nodes per block
+// shorten that path).
+static int batch_closure_nodes(hrlb_sim* const* sims, int nsims) {
+  const long long ncu = device_cus();
+  for (int nb = 4;; nb *= 2) {
+    long long items = 0;
+    size_t lds = 0;
+    for (int k = 0; k < nsims; ++k) {
+      const Shape& sh = sims[k]->sh;
+      items += ((long long)sh.B * sh.S + nb - 1) / nb + sh.B;
+      lds = std::max(lds, closure_lds_bytes_for(sh, nb));
+    }
+    if (nb == CL_NODES || items <= ncu * batch_closure_blocks_per_cu(lds)) return nb;
+  }
+}
+
+static void batch_sizes(hrlb_sim* const* sims, int nsims, int cells, int waves, int nb, int* max_tiles,
+                        int* max_items) {
   long long t = 0, it = 0;
   for (int k = 0; k < nsims; ++k) {
     const Shape& sh = sims[k]->sh;
     const int nvb = (sh.V + 64 * waves - 1) / (64 * waves), nch = (sh.S + cells - 1) / cells;
     t += (long long)sh.B * nvb * nch;
-    const int total = sh.B * sh.S, nb = closure_nodes_for(total);
+    const int total = sh.B * sh.S;
     it += (total + nb - 1) / nb + sh.B;
   }
   *max_tiles = (int)t;
@@ -615,14 +643,42 @@ int hrlb_batch_bytes(hrlb_sim* const* sims, int nsims, int cells, int waves, siz
   int rc = batch_check(sims, nsims, cells, waves);
   if (rc != HRLB_OK) return rc;
   int mt, mi;
-  batch_sizes(sims, nsims, cells, waves, &mt, &mi);
+  batch_sizes(sims, nsims, cells, waves, batch_closure_nodes(sims, nsims), &mt, &mi);
   *bytes = batch_bytes_of(nsims, mt, mi);
   return HRLB_OK;
 }
 
-// rewrite the tile table from the active flags (stream-ordered upload, then synchronise so
-// the host staging vector may be released)
-static int batch_upload_tiles(hrlb_batch* bt) {
+// rewrite the tile and closure-item tables from the active flags (stream-ordered upload,
+// then synchronise so the host staging vectors may be released).  A retired instance keeps
+// no stage tile and no wall item; a closure node block stays while any instance it covers
+// is active.
+static int batch_upload_tables(hrlb_batch* bt) {
+  std::vector<int> items;
+  items.reserve((size_t)bt->max_items * 2);
+  for (size_t k = 0; k < bt->sims.size(); ++k) {
+    const Shape& sh = bt->sims[k]->sh;
+    const int* act = bt->active.data() + bt->inst_offset[k];
+    const long long total = (long long)sh.B * sh.S;
+    const int node_blocks = (int)((total + bt->nb - 1) / bt->nb);
+    for (int blk = 0; blk < node_blocks; ++blk) {
+      const long long g0 = (long long)blk * bt->nb, g1 = std::min(total, g0 + bt->nb) - 1;
+      bool any = false;
+      for (long long b = g0 / sh.S; b <= g1 / sh.S && !any; ++b) any = act[b] != 0;
+      if (!any) continue;
+      items.push_back((int)k);
+      items.push_back(blk);
+    }
+    for (int b = 0; b < sh.B; ++b) {
+      if (!act[b]) continue;
+      items.push_back((int)k);
+      items.push_back(node_blocks + b);
+    }
+  }
+  bt->nitems = (int)(items.size() / 2);
+  if (!items.empty())
+    HIP_TRY(hipMemcpyAsync(bt->d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, bt->stream),
+            "batch: item upload");
+  HIP_TRY(hipMemcpyAsync(bt->d_nitems, &bt->nitems, sizeof(int), hipMemcpyHostToDevice, bt->stream), "batch: item upload");
   std::vector<int> tiles;
   tiles.reserve((size_t)bt->max_tiles * 4);
   for (size_t k = 0; k < bt->sims.size(); ++k) {
@@ -656,7 +712,8 @@ int hrlb_batch_create(hrlb_sim* const* sims, int nsims, int cells, int waves, vo
   if (rc != HRLB_OK) return rc;
   if (!d_work || ((uintptr_t)d_work & 255)) return fail(HRLB_EINVAL, "batch_create: work buffer NULL or misaligned");
   int mt, mi;
-  batch_sizes(sims, nsims, cells, waves, &mt, &mi);
+  const int nb = batch_closure_nodes(sims, nsims);
+  batch_sizes(sims, nsims, cells, waves, nb, &mt, &mi);
   if (work_bytes < batch_bytes_of(nsims, mt, mi)) return fail(HRLB_ENOMEM, "batch_create: work buffer too small");
   for (int a = 0; a < nsims; ++a)
     for (int b = a + 1; b < nsims; ++b)
@@ -668,6 +725,7 @@ int hrlb_batch_create(hrlb_sim* const* sims, int nsims, int cells, int waves, vo
   bt->stream = (hipStream_t)stream;
   bt->max_tiles = mt;
   bt->max_items = mi;
+  bt->nb = nb;
   bt->gexec = nullptr;
   bt->cap_stream = nullptr;
   char* w = (char*)d_work;
@@ -681,7 +739,6 @@ int hrlb_batch_create(hrlb_sim* const* sims, int nsims, int cells, int waves, vo
   w += align256((size_t)mi * 2 * sizeof(int));
   bt->d_nitems = (int*)w;
   std::vector<GroupDesc> groups(nsims);
-  std::vector<int> items;
   int total_inst = 0;
   bt->lds_closure = 0;
   for (int k = 0; k < nsims; ++k) {
@@ -703,39 +760,29 @@ int hrlb_batch_create(hrlb_sim* const* sims, int nsims, int cells, int waves, vo
     g.nch = (sm->sh.S + cells - 1) / cells;
     g.cs = cells;
     const int total = sm->sh.B * sm->sh.S;
-    g.nb = closure_nodes_for(total);
+    g.nb = nb;
     g.node_blocks = (total + g.nb - 1) / g.nb;
     sm->part_nvb = g.nvb;
-    for (int it = 0; it < g.node_blocks + sm->sh.B; ++it) {
-      items.push_back(k);
-      items.push_back(it);
-    }
     bt->lds_closure = std::max(bt->lds_closure, closure_lds_bytes_for(sm->sh, g.nb));
     bt->inst_offset.push_back(total_inst);
     total_inst += sm->sh.B;
   }
   bt->active.assign(total_inst, 1);
-  bt->nitems = (int)(items.size() / 2);
   bt->lds_stage = stage_lds_bytes_for(waves);
   hipError_t e = hipMemcpyAsync(bt->d_groups, groups.data(), nsims * sizeof(GroupDesc), hipMemcpyHostToDevice, bt->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(bt->d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, bt->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(bt->d_nitems, &bt->nitems, sizeof(int), hipMemcpyHostToDevice, bt->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);
   if (e != hipSuccess) {
     delete bt;
     return hip_fail(e, "batch_create: upload");
   }
-  if ((rc = batch_upload_tiles(bt)) != HRLB_OK) {
+  if ((rc = batch_upload_tables(bt)) != HRLB_OK) {
     delete bt;
     return rc;
   }
-  int dev = 0, ncu = 256;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  // persistent grids: a few resident blocks per CU loop over the tables
-  bt->grid_stage = std::max(1, std::min(mt, ncu * 16 / waves));
-  bt->grid_closure = std::max(1, std::min(mi, ncu * 8));
+  // the stage grid is persistent (a few resident blocks per CU loop over the tile table);
+  // the closure grid has one block per item (blocks past the live item count return)
+  bt->grid_stage = std::max(1, std::min(mt, device_cus() * 16 / waves));
+  bt->grid_closure = std::max(1, mi);
   *out = bt;
   return HRLB_OK;
 }
@@ -811,7 +858,7 @@ int hrlb_batch_residual(hrlb_batch* bt, double* h_out) {
 int hrlb_batch_set_active(hrlb_batch* bt, const int* active) {
   if (!bt || !active) return fail(HRLB_EINVAL, "batch_set_active: NULL argument");
   for (size_t i = 0; i < bt->active.size(); ++i) bt->active[i] = active[i] ? 1 : 0;
-  return batch_upload_tiles(bt);
+  return batch_upload_tables(bt);
 }
 
 int hrlb_batch_info(const hrlb_batch* bt, int* ntiles, int* nitems, int* grid_stage, int* grid_closure) {

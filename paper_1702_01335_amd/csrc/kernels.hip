@@ -438,7 +438,6 @@ __global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, cons
 // closure: 64 nodes per block (one lane per node for the scalar closure), plus one wall
 // block per instance
 
-constexpr int CL_NODES = 64;             // most nodes per closure block
 
 // one closure work item: node block `blk` (< node_blocks) or the wall of instance
 // blk - node_blocks; 64 threads; cl_lds holds the closure LDS (size closure_lds_doubles)
@@ -1086,6 +1085,12 @@ int launch_residual(const Shape& sh, const DevPtrs& d, int nres, void* stream) {
 size_t stage_lds_bytes_for(int waves) { return stage_lds_bytes(waves); }
 size_t closure_lds_bytes_for(const Shape& sh, int nb) { return closure_lds_doubles(sh, nb) * sizeof(double); }
 int closure_nodes_for(int total_nodes) { return closure_nodes_per_block(total_nodes); }
+int batch_closure_blocks_per_cu(size_t lds_bytes) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_closure_kernel, 64, lds_bytes) != hipSuccess || n < 1)
+    return 8;
+  return n;
+}
 
 int launch_batch_stage(int stage, const GroupDesc* groups, const void* tiles, const int* ntiles, int grid, int waves,
                        size_t lds_bytes, void* stream) {

@@ -74,9 +74,12 @@ def test_batch_retirement_freezes_instances():
     bt = hrlb.Batch(sims, CELLS, WAVES)
     bt.step(3)
     before = [s.get_state().cpu().numpy() for s in sims]
+    items_all = bt.info()['closure_items']
     active = np.ones(bt.B, dtype=np.int32)
     active[[0, 3, 5]] = 0       # instance 0 of group 0, instance 0 of group 2, instance 2 of group 2
     bt.set_active(active)
+    # retired instances keep no wall item and no closure node block of their own
+    assert bt.info()['closure_items'] <= items_all - 3
     bt.step(3)
     after = [s.get_state().cpu().numpy() for s in sims]
     assert np.array_equal(after[0][0], before[0][0])
@@ -89,6 +92,14 @@ def test_batch_retirement_freezes_instances():
     bt2.step(6)
     F2 = ref[2].get_state().cpu().numpy()
     assert np.abs(after[2][1] - F2[1]).max() / np.abs(F2[1]).max() <= 1e-15
+    # re-activated, a frozen instance resumes from its own state: 3 + 3 active steps equal
+    # 6 uninterrupted ones
+    bt.set_active(np.ones(bt.B, dtype=np.int32))
+    assert bt.info()['closure_items'] == items_all
+    bt.step(3)
+    F0 = sims[0].get_state().cpu().numpy()[0]
+    R0 = ref[0].get_state().cpu().numpy()[0]
+    assert np.abs(F0 - R0).max() / np.abs(R0).max() <= 1e-15
 
 
 def test_sweep_runs_to_steady_with_retirement():
