@@ -968,13 +968,12 @@ __global__ void __launch_bounds__(64) batch_closure_kernel(const GroupDesc* __re
                                                            const int2* __restrict__ items, const int* __restrict__ nitems,
                                                            int stage) {
   extern __shared__ double cl_lds[];
-  const int n = *nitems;
-  for (int t = blockIdx.x; t < n; t += gridDim.x) {
-    const int2 it = items[t];
-    const GroupDesc& g = groups[it.x];
-    closure_block(g.sh, g.d, g.d.F[stage - 1], g.nvb, nullptr, it.y, g.node_blocks, g.nb, cl_lds);
-    __syncthreads();
-  }
+  // one block per item; the grid is sized for every item, blocks past the live count return
+  const int t = blockIdx.x;
+  if (t >= *nitems) return;
+  const int2 it = items[t];
+  const GroupDesc& g = groups[it.x];
+  closure_block(g.sh, g.d, g.d.F[stage - 1], g.nvb, nullptr, it.y, g.node_blocks, g.nb, cl_lds);
 }
 
 __global__ void __launch_bounds__(256) residual_kernel(Shape sh, DevPtrs d, int nres) {
