@@ -779,9 +779,8 @@ int hrlb_batch_create(hrlb_sim* const* sims, int nsims, int cells, int waves, vo
     delete bt;
     return rc;
   }
-  // the stage grid is persistent (a few resident blocks per CU loop over the tile table);
-  // the closure grid has one block per item (blocks past the live item count return)
-  bt->grid_stage = std::max(1, std::min(mt, device_cus() * 16 / waves));
+  // one block per tile and per closure item (blocks past the live counts return)
+  bt->grid_stage = std::max(1, mt);
   bt->grid_closure = std::max(1, mi);
   *out = bt;
   return HRLB_OK;

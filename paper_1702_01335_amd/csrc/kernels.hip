@@ -948,20 +948,19 @@ template <int STAGE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) batch_stage_kernel(const GroupDesc* __restrict__ groups,
                                                           const int4* __restrict__ tiles, const int* __restrict__ ntiles) {
   extern __shared__ double lds[];
-  const int n = *ntiles;
-  for (int t = blockIdx.x; t < n; t += gridDim.x) {
-    const int4 tl = tiles[t];
-    const GroupDesc& g = groups[tl.x];
-    const double* Fin = g.d.F[STAGE - 1];
-    double* Fout = g.d.F[STAGE % 3];
-    if (g.sh.scheme == 1)
-      stage_tile<1, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
-    else if (g.sh.scheme == 2)
-      stage_tile<2, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
-    else
-      stage_tile<0, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
-    __syncthreads();
-  }
+  // one block per tile; the grid is sized for every tile, blocks past the live count return
+  const int t = blockIdx.x;
+  if (t >= *ntiles) return;
+  const int4 tl = tiles[t];
+  const GroupDesc& g = groups[tl.x];
+  const double* Fin = g.d.F[STAGE - 1];
+  double* Fout = g.d.F[STAGE % 3];
+  if (g.sh.scheme == 1)
+    stage_tile<1, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
+  else if (g.sh.scheme == 2)
+    stage_tile<2, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
+  else
+    stage_tile<0, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
 }
 
 __global__ void __launch_bounds__(64) batch_closure_kernel(const GroupDesc* __restrict__ groups,
