@@ -52,6 +52,15 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// a pointer into device memory re-typed to the global address space.  Pointers that reach
+// a kernel through memory (the batched kernels' group descriptors) are generic to the
+// compiler, which would otherwise access them with flat instructions; flat accesses count
+// on both wait counters, so a wait for a scalar load would also wait for them.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // WENO-5 reconstruction at the interface downstream of c from the upwind-ordered
 // stencil (a, b, c, d, e) (App. A.3; candidates of Eq. weno5_flux, indicators of
 // Eq. weno_sigma, weights of Eq. weno5_omega without epsilon).  The candidates are carried
@@ -335,7 +344,7 @@ __device__ __forceinline__ void load_moment_operands(const double* __restrict__ 
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     const int v = wave_v0 + 4 * t + (lane >> 4);
-    a[t] = (v < V) ? ptab[(size_t)v * 16 + (lane & 15)] : 0.0;
+    a[t] = (v < V) ? gmem(ptab)[(size_t)v * 16 + (lane & 15)] : 0.0;
   }
 }
 
@@ -380,7 +389,7 @@ __device__ __forceinline__ void store_moments(const dbl4& acc, const double* lds
   if (waves == 1) {
     const int lane = threadIdx.x, n = lane & 15, m0 = lane >> 4;
     if (n < cnt) {
-      double* o = out + (size_t)n * node_stride + m0;
+      auto o = gmem(out + (size_t)n * node_stride + m0);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         if (m0 + 4 * r < NMOM) o[4 * r] = acc[r];
@@ -391,7 +400,7 @@ __device__ __forceinline__ void store_moments(const dbl4& acc, const double* lds
     const int n = idx / NMOM, q = idx - n * NMOM;
     double s = 0.0;
     for (int w = 0; w < waves; ++w) s += lds_red[w * RED_WAVE + n * 16 + q];
-    out[(size_t)n * node_stride + q] = s;
+    gmem(out)[(size_t)n * node_stride + q] = s;
   }
 }
 
@@ -450,9 +459,9 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
     // wall density: zero net mass flux through x = L/2 (App. A.4); the outgoing fluxes
     // (p_x > 0) use the extrapolated ghosts, the incoming ones are p_x n_w F^eq_w exactly.
     const int b = blk - node_blocks;
-    const InstDev* in = d.inst + b;
+    const auto in = gmem(d.inst + b);
     const int V = sh.V;
-    const double* F = Fin + (size_t)b * S * V;
+    const auto F = gmem(Fin + (size_t)b * S * V);
     double ex[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) ex[q] = in->ex[q];
@@ -463,7 +472,7 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int v = min(v0 + 64 * k, V - 1);
-        px[k] = (v0 + 64 * k < V) ? d.px[v / sh.QyQz] : 0.0;
+        px[k] = (v0 + 64 * k < V) ? gmem(d.px)[v / sh.QyQz] : 0.0;
         f3[k] = F[(size_t)(S - 3) * V + v];
         f2[k] = F[(size_t)(S - 2) * V + v];
         f1[k] = F[(size_t)(S - 1) * V + v];
@@ -481,8 +490,8 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
     acc = wave_sum(acc);
     if (lane == 0) {
       const double nw = -acc / in->wall_den;
-      d.nw[b] = nw;
-      if (!(nw > 0.0) || !isfinite(nw)) d.flags[b] = 1;
+      gmem(d.nw)[b] = nw;
+      if (!(nw > 0.0) || !isfinite(nw)) gmem(d.flags)[b] = 1;
     }
     return;
   }
@@ -512,7 +521,11 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int e = e0 + 64 * k;
-        x[k] = (e < n1) ? d.phix[e] : (e < n2) ? d.phiy[e - n1] : (e < n3) ? d.phiz[e - n2] : (e < n4) ? d.cx[e - n3] : 0.0;
+        x[k] = (e < n1)   ? gmem(d.phix)[e]
+               : (e < n2) ? gmem(d.phiy)[e - n1]
+               : (e < n3) ? gmem(d.phiz)[e - n2]
+               : (e < n4) ? gmem(d.cx)[e - n3]
+                          : 0.0;
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -535,7 +548,7 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
         for (int j = 0; j < 4; ++j) {
           const int nd = j0 + n0 + 4 * j;
           const bool ok = nd < nblk_nodes && q < NMOM;
-          const double* src = d.partials + ((size_t)(g0 + (ok ? nd : 0)) * nvb) * PART_STRIDE + q;
+          const auto src = gmem(d.partials + ((size_t)(g0 + (ok ? nd : 0)) * nvb) * PART_STRIDE + q);
 #pragma unroll
           for (int t = 0; t < 4; ++t) x[j][t] = (ok && vb0 + t < nvb) ? src[(size_t)(vb0 + t) * PART_STRIDE] : 0.0;
         }
@@ -554,7 +567,7 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
   const bool live = lane < nblk_nodes;
   const int g = g0 + (live ? lane : 0), b = g / S, c = g - b * S;
   (void)c;
-  const InstDev* in = d.inst + b;
+  const auto in = gmem(d.inst + b);
   const double* M = msum + lane * PART_STRIDE;
   const double n = live ? M[0] : 1.0;
   const double ux = live ? M[1] / n : 0.0, uy = live ? M[2] / n : 0.0, uz = live ? M[3] / n : 0.0;
@@ -571,7 +584,7 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
   double* sc = scal + lane * SC;
   if (live) {
     if (mom_out) {
-      double* o = mom_out + (size_t)g * 14;
+      const auto o = gmem(mom_out + (size_t)g * 14);
       o[0] = n;
       o[1] = ux;
       o[2] = uy;
@@ -587,7 +600,7 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
       o[12] = qy;
       o[13] = qz;
     }
-    if (bad) d.flags[b] = 1;
+    if (bad) gmem(d.flags)[b] = 1;
     // relaxation time from mu = tau n T
     double tau;
     if (in->law == 0.0)
@@ -598,7 +611,7 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
       tau = in->kn * M_SQRT1_2;  // linearised (low Mach) regime, Eq. knLuo: tau = k / sqrt(2)
     const double invtau = (in->collisionless != 0.0 || bad) ? 0.0 : 1.0 / tau;
     const double Cs = (1.0 - in->pr) / (n * T * T);
-    double* rec = d.rec + (size_t)g * sh.rec_len;
+    const auto rec = gmem(d.rec + (size_t)g * sh.rec_len);
     rec[0] = ux;
     rec[1] = uy;
     rec[2] = uz;
@@ -608,7 +621,7 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
     rec[6] = qx;
     rec[7] = qy;
     rec[8] = qz;
-    rec[9] = in->dt * d.inv_dx[g];
+    rec[9] = in->dt * gmem(d.inv_dx)[g];
     // projection coefficients of the 1D Maxwellian factors (Sec. III)
     double I[NX_MAX + 1], J[NX_MAX + 1], a[NYZ_MAX + 1];
     const double Tc = bad ? 1.0 : T;
@@ -651,7 +664,7 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
       const int jk = e - nx2, j = jk / sh.Qz, k = jk - j * sh.Qz;
       val = gyz[nd * Qyz + j] * gyz[nd * Qyz + sh.Qy + k];
     }
-    d.rec[(size_t)(g0 + nd) * sh.rec_len + REC_HEAD + e] = val;
+    gmem(d.rec)[(size_t)(g0 + nd) * sh.rec_len + REC_HEAD + e] = val;
   }
 }
 
@@ -690,7 +703,7 @@ __device__ __forceinline__ double raw_node(const double* __restrict__ Fb, int c,
   // Lanes beyond V read a valid velocity; their results are never stored or summed.
   const int node = (c < 0) ? (-c - 1) : min(c, S - 1);
   const int vel = (c < 0) ? vm : vcl;
-  return Fb[(size_t)node * V + vel];
+  return gmem(Fb)[(size_t)node * V + vel];
 }
 
 // buffer resource over an instance's array (raw, unbounded: every offset the kernels form is
@@ -745,14 +758,14 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   const bool active = v < V;
   const int vv = active ? v : V - 1;
   const int i = vv / sh.QyQz, jk = vv - i * sh.QyQz, j = jk / sh.Qz, k = jk - j * sh.Qz;
-  const double px = d.px[i], py = d.py[j], pz = d.pz[k];
+  const double px = gmem(d.px)[i], py = gmem(d.py)[j], pz = gmem(d.pz)[k];
   const bool pos = px > 0.0;
   const int vm = ((2 * Qx - 1 - i) * sh.Qy + (sh.Qy - 1 - j)) * sh.Qz + k;  // bounce-back partner
   const size_t base = (size_t)b * S * V;
   const double* Fb = Fin + base;
   const InstDev* in = d.inst + b;
   const double* ex = in->ex;
-  const double ghost_in = active ? d.nw[b] * d.g_wall[(size_t)b * V + vv] : 0.0;
+  const double ghost_in = active ? gmem(d.nw)[b] * gmem(d.g_wall)[(size_t)b * V + vv] : 0.0;
   const int wave_v0 = vb * blockDim.x + wave * 64;
   const int s0 = ch * cs;
   const int nloc = min(cs, S - s0);
@@ -901,7 +914,7 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
     // covers them and the prefetched loads together, and the march starts each group
     // with no store outstanding, so its waits stay partial.
     if (active) {
-      double* dst = Fout + base + (size_t)(s0 + g) * V + v;
+      auto dst = gmem(Fout + base + (size_t)(s0 + g) * V + v);
       for (int u = 0; u < cnt; ++u) dst[(size_t)u * V] = ft[u * FT_LD + lane];
     }
     if (g > 0) store_moments(acc, lds_red, waves, 16, part + (size_t)(g - 16) * nstride, nstride);
@@ -925,7 +938,7 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
     if (threadIdx.x < 2) {
       double s = 0.0;
       for (int wv = 0; wv < waves; ++wv) s += lds_res[2 * wv + threadIdx.x];
-      d.resid_part[((size_t)b * nvb * nch + (size_t)vb * nch + ch) * 2 + threadIdx.x] = s;
+      gmem(d.resid_part)[((size_t)b * nvb * nch + (size_t)vb * nch + ch) * 2 + threadIdx.x] = s;
     }
   }
 }
