@@ -138,8 +138,9 @@ static Shape make_shape(const QuadTables& t, int S, int B, int scheme) {
   sh.S = S;
   sh.B = B;
   sh.scheme = scheme;
+  // whole 128-byte lines per node record
   int rl = REC_HEAD + 2 * t.Qx + sh.QyQz;
-  sh.rec_len = (rl + 1) & ~1;
+  sh.rec_len = (rl + 15) & ~15;
   return sh;
 }
 

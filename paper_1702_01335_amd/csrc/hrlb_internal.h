@@ -13,7 +13,7 @@ constexpr int NYZ_MAX = 15;  // largest full-range expansion order on y, z (Q <=
 constexpr int QYZ_MAX = 16;
 constexpr int QX_MAX = 128;
 constexpr int REC_HEAD = 16;  // scalars at the head of a per-node closure record
-constexpr int PART_STRIDE = 16;  // doubles per (block, node) moment partial (13 used)
+constexpr int PART_STRIDE = 16;  // doubles per (block, node) moment partial: 13 moments, 3 zero
 constexpr int NMOM = 13;
 constexpr int MAX_WAVES = 4;   // waves per stage-kernel workgroup (LDS: ~10.4 KB per wave)
 
@@ -74,7 +74,7 @@ struct Shape {
   int Qx, Nx, Qy, Ny, Qz, Nz;
   int V, QyQz, S, B;
   int scheme;
-  int rec_len;        // REC_HEAD + 2 Qx + Qy Qz, rounded up to even
+  int rec_len;        // REC_HEAD + 2 Qx + Qy Qz, rounded up to a multiple of 16 (whole lines)
 };
 
 // One uniform group (one sim) inside a batch, as the batched kernels see it.

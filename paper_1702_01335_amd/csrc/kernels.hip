@@ -383,7 +383,9 @@ __device__ __forceinline__ void park_moments(double* lds_red, const dbl4& acc, i
 
 // store the moment sums of cnt nodes, node-major with node_stride: from the registers of a
 // one-wave block (register r of lane l holds moment 4 r + l / 16 of node l % 16), or from
-// the waves' parked contractions summed in LDS
+// the waves' parked contractions summed in LDS.  All 16 slots of a node's row are written
+// (the contraction leaves slots 13..15 zero), so each row is one whole 128-byte line: rows
+// written in part cost measurably more.
 __device__ __forceinline__ void store_moments(const dbl4& acc, const double* lds_red, int waves, int cnt,
                                               double* __restrict__ out, int node_stride) {
   if (waves == 1) {
@@ -392,12 +394,12 @@ __device__ __forceinline__ void store_moments(const dbl4& acc, const double* lds
       auto o = gmem(out + (size_t)n * node_stride + m0);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (m0 + 4 * r < NMOM) o[4 * r] = acc[r];
+        o[4 * r] = acc[r];
     }
     return;
   }
-  for (int idx = threadIdx.x; idx < cnt * NMOM; idx += blockDim.x) {
-    const int n = idx / NMOM, q = idx - n * NMOM;
+  for (int idx = threadIdx.x; idx < cnt * PART_STRIDE; idx += blockDim.x) {
+    const int n = idx / PART_STRIDE, q = idx - n * PART_STRIDE;
     double s = 0.0;
     for (int w = 0; w < waves; ++w) s += lds_red[w * RED_WAVE + n * 16 + q];
     gmem(out)[(size_t)n * node_stride + q] = s;
