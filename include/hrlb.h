@@ -212,8 +212,10 @@ int hrlb_get_timing(hrlb_sim* sim, double* ms, long long* launches);
 /*
  * Batches: advance several sims -- each a group of instances sharing one velocity set,
  * node count and scheme, the groups differing in any of them -- together, with one
- * persistent launch per kernel per RK3 stage.  The launches walk device-side tables of
- * (group, instance, velocity block, node chunk) tiles and of closure work items; one RK3
+ * launch per kernel per RK3 stage.  The launches read device-side tables of
+ * (group, instance, velocity block, node chunk) tiles and of closure work items (one block
+ * each; retired instances drop out of both tables, so blocks past the live counts return
+ * at once); one RK3
  * step of the whole batch is captured as a HIP graph on first use and replayed.  Results
  * are those of stepping every sim alone with the same launch shape, bit for bit.
  *

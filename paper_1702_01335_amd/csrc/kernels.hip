@@ -38,14 +38,6 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
   return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
-// value of x in lane l (uniform l), as a scalar
-__device__ __forceinline__ double bcast(double x, int l) {
-  const unsigned long long u = __double_as_longlong(x);
-  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, l);
-  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), l);
-  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
-}
-
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -791,12 +783,11 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
 
   // Per-node operands, software-pipelined in rotating register sets (the node loop is
   // unrolled by PIPE, so no register with a load in flight is ever copied).  The two HBM
-  // streams, the window node c+3 and F_l, and the gathers that hit the cache (the two
-  // equilibrium factors and the node's uniform closure scalars: lane q < 10 loads record
-  // field q -- u, 1/tau, Shakhov coefficients, q, 1/dx -- broadcast with readlane where
-  // used) run PIPE nodes ahead.  All are unconditional vector loads with clamped addresses,
-  // which complete in order; each is a wave-uniform row address plus a fixed 32-bit lane
-  // offset, so no address arithmetic is repeated per lane and node.
+  // streams, the window node c+3 and F_l, and the two equilibrium-factor gathers (which hit
+  // the cache) run PIPE nodes ahead.  All are unconditional vector loads with clamped
+  // addresses, which complete in order; each is a wave-uniform row offset in a scalar
+  // register plus a fixed 32-bit lane offset, so no address arithmetic is repeated per lane
+  // and node.  The node's closure scalars are uniform and come by scalar loads (ld_sc).
   struct Far {
     double raw, fl0;
   };
@@ -957,7 +948,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) s
 }
 
 // ---------------------------------------------------------------------------------------
-// batched (ragged) launches: one persistent grid serves the tiles of every group
+// batched (ragged) launches: one grid serves the tiles of every group
 
 template <int STAGE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) batch_stage_kernel(const GroupDesc* __restrict__ groups,

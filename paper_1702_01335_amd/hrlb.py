@@ -276,7 +276,7 @@ class Solver:
 
 class Batch:
     """Several Solvers (groups of instances that differ in velocity set, node count or
-    scheme) advanced together by one persistent launch per kernel per stage, graph-captured.
+    scheme) advanced together by one launch per kernel per stage, graph-captured.
     All solvers must use the torch stream current at construction."""
 
     def __init__(self, solvers, cells, waves):

@@ -1,5 +1,5 @@
 """Batched (ragged) execution: groups that differ in velocity set, node count and scheme,
-advanced by one persistent launch per kernel per stage, must reproduce stepping each group
+advanced by one launch per kernel per stage, must reproduce stepping each group
 alone with the same launch shape, and retired instances must stop advancing."""
 import numpy as np
 import pytest
