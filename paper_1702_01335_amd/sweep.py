@@ -107,10 +107,11 @@ class Sweep:
         torch.cuda.synchronize()
         return self.cells, self.waves, ms
 
-    def run_to_steady(self, tol, max_steps, check_every=200):
+    def run_to_steady(self, tol, max_steps, check_every=200, progress=None):
         """Step until every instance's residual is below tol (retiring converged ones) or the
         step budget is spent.  Returns per-instance steps in batch order (-1 if not
-        converged), the final residuals and the wall time."""
+        converged), the final residuals and the wall time.  progress, if given, is called
+        after every residual check with (steps done, instances still active)."""
         steps = np.full(self.B, -1)
         active = np.ones(self.B, dtype=np.int32)
         done = 0
@@ -127,6 +128,8 @@ class Sweep:
                 active[newly] = 0
                 if active.any():
                     self.batch.set_active(active)
+            if progress is not None:
+                progress(done, int(active.sum()))
         wall = time.perf_counter() - t0
         return steps, R, wall
 
@@ -178,7 +181,14 @@ def main():
     sw = Sweep(sample(a.instances, a.seed))
     c, w, _ = sw.autotune(probe_steps=3)
     print(json.dumps({'groups': [[k[0], k[1], len(i)] for k, i, _ in sw.groups], 'launch': [c, w]}), flush=True)
-    steps, R, wall = sw.run_to_steady(a.tol, a.max_steps, a.check_every)
+    t_last = [time.perf_counter()]
+
+    def progress(done, n_active):
+        if time.perf_counter() - t_last[0] > 20.0:
+            t_last[0] = time.perf_counter()
+            print(json.dumps({'steps': done, 'active': n_active}), flush=True)
+
+    steps, R, wall = sw.run_to_steady(a.tol, a.max_steps, a.check_every, progress)
     print(json.dumps({'batched_wall_s': wall, 'converged': int((steps > 0).sum())}), flush=True)
     # single-instance step time per shape
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
