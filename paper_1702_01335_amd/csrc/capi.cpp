@@ -107,7 +107,7 @@ WorkLayout work_layout(const Shape& sh) {
   L.cx = take((size_t)(sh.Nx + 1) * (sh.Nx + 1) * dsz);
   L.phiy = take((size_t)sh.Qy * (sh.Ny + 1) * dsz);
   L.phiz = take((size_t)sh.Qz * (sh.Nz + 1) * dsz);
-  L.ptab = take((size_t)sh.V * 16 * dsz);
+  L.ptab = take((size_t)ptab_blocks(sh.V) * 1024 * dsz);
   L.inst = take((size_t)sh.B * sizeof(InstDev));
   L.inv_dx = take((size_t)sh.B * sh.S * dsz);
   L.g_rest = take((size_t)sh.B * sh.V * dsz);

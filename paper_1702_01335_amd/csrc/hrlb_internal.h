@@ -16,6 +16,9 @@ constexpr int REC_HEAD = 16;  // scalars at the head of a per-node closure recor
 constexpr int PART_STRIDE = 16;  // doubles per (block, node) moment partial: 13 moments, 3 zero
 constexpr int NMOM = 13;
 constexpr int MAX_WAVES = 4;   // waves per stage-kernel workgroup (LDS: ~10.4 KB per wave)
+// 64-velocity blocks of the moment-multiplier table: those of V, plus the whole idle waves
+// a workgroup of up to MAX_WAVES waves can hold past V
+constexpr int ptab_blocks(int V) { return (V + 63) / 64 + MAX_WAVES - 1; }
 
 // Host quadrature tables (double, rounded from long double).
 struct QuadTables {
@@ -52,7 +55,7 @@ struct DevPtrs {
   const double* cx;   // [Nx+1][Nx+1]
   const double* phiy; // [Qy][Ny+1]
   const double* phiz; // [Qz][Nz+1]
-  double* ptab;       // [V][16]: moment multipliers of each velocity (filled on the device)
+  double* ptab;       // moment multipliers in MFMA operand order, [ptab_blocks(V)][8][64][2] (filled on the device)
   // per instance
   InstDev* inst;      // [B]
   double* inv_dx;     // [B][S]

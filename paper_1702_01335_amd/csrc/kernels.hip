@@ -182,13 +182,24 @@ __global__ void __launch_bounds__(256) setup_tables_kernel(Shape sh, DevPtrs d) 
   }
   for (int k = threadIdx.x; k < sh.Qz; k += blockDim.x) gz0[k] = full_node(d.phiz, sh.Nz, k, a0);
   if (b == 0) {
-    // moment multipliers of each velocity, the A operand of the moment contraction
-    for (int v = threadIdx.x; v < sh.V; v += blockDim.x) {
-      const int i = v / sh.QyQz, jk = v - i * sh.QyQz, j = jk / sh.Qz, k = jk - j * sh.Qz;
-      const double px = d.px[i], py = d.py[j], pz = d.pz[k], p2 = px * px + py * py + pz * pz;
-      const double m[16] = {1.0, px, py, pz, px * px, py * py, pz * pz, px * py, px * pz, py * pz,
-                            p2 * px, p2 * py, p2 * pz, 0.0, 0.0, 0.0};
-      for (int q = 0; q < 16; ++q) d.ptab[(size_t)v * 16 + q] = m[q];
+    // moment multipliers of each velocity (1, p, p_a p_b, p^2 p), the A operand of the
+    // moment contraction, in operand order: for the wave of velocities 64 w .. 64 w + 63,
+    // operand t of lane l is multiplier l % 16 of velocity 64 w + 4 t + l / 16, stored
+    // [w][t / 2][l][t % 2] so that a lane reads two operands with one 16-byte load; zero
+    // past V (and for MAX_WAVES - 1 waves more, which whole idle waves read)
+    const int n = ptab_blocks(sh.V) * 1024;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+      const int w = idx >> 10, rem = idx & 1023, t = 2 * (rem >> 7) + (rem & 1), l = (rem >> 1) & 63;
+      const int v = 64 * w + 4 * t + (l >> 4), q = l & 15;
+      double val = 0.0;
+      if (v < sh.V && q < NMOM) {
+        const int i = v / sh.QyQz, jk = v - i * sh.QyQz, j = jk / sh.Qz, k = jk - j * sh.Qz;
+        const double px = d.px[i], py = d.py[j], pz = d.pz[k], p2 = px * px + py * py + pz * pz;
+        const double m[NMOM] = {1.0, px, py, pz, px * px, py * py, pz * pz, px * py, px * pz, py * pz,
+                                p2 * px, p2 * py, p2 * pz};
+        val = m[q];
+      }
+      d.ptab[idx] = val;
     }
   }
   __syncthreads();
@@ -333,10 +344,14 @@ constexpr int RED_WAVE = 16 * 16;         // doubles per wave of reduced moments
 // load this lane's A operands: a[t] = P[v0 + 4t + lane/16][lane % 16] (0 beyond V)
 __device__ __forceinline__ void load_moment_operands(const double* __restrict__ ptab, int wave_v0, int V, int lane,
                                                      double* a) {
+  (void)V;  // the table is zero past V
+  typedef double pair_t __attribute__((ext_vector_type(2)));
+  const auto p = gmem(reinterpret_cast<const pair_t*>(ptab) + (size_t)(wave_v0 >> 6) * 512 + lane);
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const int v = wave_v0 + 4 * t + (lane >> 4);
-    a[t] = (v < V) ? gmem(ptab)[(size_t)v * 16 + (lane & 15)] : 0.0;
+  for (int t2 = 0; t2 < 8; ++t2) {
+    const pair_t x = p[t2 * 64];
+    a[2 * t2] = x.x;
+    a[2 * t2 + 1] = x.y;
   }
 }
 
@@ -348,14 +363,11 @@ __device__ __forceinline__ dbl4 moment_mfma(const double* ft, const double* a, i
   return acc;
 }
 
-// after every wave has stored its group of up to 16 node rows in its tile: contract with
-// the multipliers of the wave's velocities (A operands loaded here, from the small,
-// cache-resident multiplier table, so they hold no registers during the march), sum over
-// the block's waves and write the block's partials for nodes s .. s+cnt-1.
-// Moment sums of a group of 16 node rows.  The wave contracts its tile with the
-// multipliers of its 64 velocities on the matrix cores; the 13 sums of node n end up in
-// the lane pair that holds D[.][n].  A block of one wave stores them straight from these
-// registers; with more waves they are added across waves in LDS first.
+// Moment sums of a group of 16 node rows, once every wave has stored its rows in its tile:
+// the wave contracts its tile with the multipliers of its 64 velocities on the matrix
+// cores (A operands loaded here; the stage kernel keeps them in registers instead); the 13
+// sums of node n end up in the lanes that hold D[.][n].  A block of one wave stores them
+// straight from these registers; with more waves they are added across waves in LDS first.
 __device__ __forceinline__ dbl4 moment_contract(const double* lds_ft, const double* __restrict__ ptab, int wave_v0,
                                                 int V, int wave, int lane) {
   double a[16];
@@ -881,6 +893,10 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
 
   int last_cnt = 0, last_g = 0;
   dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  // the contraction's A operands (the multipliers of the wave's 64 velocities) stay in
+  // registers for the whole tile: eight 16-byte loads once instead of per group
+  double pa[16];
+  load_moment_operands(d.ptab, wave_v0, V, lane, pa);
   for (int g = 0; g < nloc; g += 16) {
     const int cnt = min(16, nloc - g);
     // the 16 nodes of a group as straight-line code: the load counter's state is then known
@@ -911,7 +927,8 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
       for (int u = 0; u < cnt; ++u) dst[(size_t)u * V] = ft[u * FT_LD + lane];
     }
     if (g > 0) store_moments(acc, lds_red, waves, 16, part + (size_t)(g - 16) * nstride, nstride);
-    acc = moment_contract(lds_ft, d.ptab, wave_v0, V, wave, lane);
+    __syncthreads();
+    acc = moment_mfma(lds_ft + wave * FT_WAVE, pa, lane);
     if (waves > 1) {
       park_moments(lds_red, acc, wave, lane);
     }
