@@ -38,8 +38,9 @@ def parse():
     ap.add_argument('--no-cpu', action='store_true')
     ap.add_argument('--eager', action='store_true', help='launch kernels one by one instead of replaying a HIP graph')
     ap.add_argument('--no-tune', action='store_true', help='keep the default launch shape instead of autotuning it')
-    ap.add_argument('--tune-cache', default=os.path.join(ROOT, 'paper_1702_01335_amd', 'tuned_launch.jsonl'),
-                    help='JSON-lines cache of autotuned launch shapes (a shape found there is used without timing)')
+    ap.add_argument('--tune-cache', default=None,
+                    help='JSON-lines cache of autotuned launch shapes; a shape found there is used without timing '
+                         '(default: time every shape on this GPU)')
     ap.add_argument('--copy-probe-mib', type=int, default=0,
                     help='also run one device copy of this size (calibrates HBM byte counters under a profiler)')
     ap.add_argument('--cpu-seconds', type=float, default=15.0)
@@ -88,10 +89,10 @@ def time_steps(solver, steps, warmup):
 
 def profiled_traffic(tag, bytes_per_launch, cells, waves):
     """HBM bytes per stage-kernel launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    passes (profiles/<tag>_traffic.json), or None when the kernel source or the launch shape
-    differs from the one profiled."""
+    passes of this launch shape (profiles/<tag>_c<cells>w<waves>_traffic.json), or None when
+    that shape was not profiled or the kernel source differs from the one profiled."""
     import hashlib
-    path = os.path.join(ROOT, 'profiles', f'{tag}_traffic.json')
+    path = os.path.join(ROOT, 'profiles', f'{tag}_c{cells}w{waves}_traffic.json')
     if not os.path.exists(path):
         return None
     tr = json.load(open(path))
@@ -259,7 +260,7 @@ def main():
         solver.set_launch(args.cells or c0, args.waves or w0)
     elif not args.no_tune:
         # the library's autotuner times every (node chunk, waves) shape on this state
-        c_t, w_t, ms_t = solver.autotune(probe_steps=3, cache_path=args.tune_cache)
+        c_t, w_t, ms_t = solver.autotune(probe_steps=5, cache_path=args.tune_cache)
         tuned = dict(cells=c_t, waves=w_t, probe_ms_per_step=ms_t if ms_t >= 0 else None,
                      source='timed now' if ms_t >= 0 else args.tune_cache)
     cells, waves = solver.get_launch()

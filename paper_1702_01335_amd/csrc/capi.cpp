@@ -537,35 +537,58 @@ int hrlb_autotune(hrlb_sim* s, int probe_steps, const char* cache_path, int* bes
   HIP_TRY(hipEventCreate(&e0), "autotune: event");
   HIP_TRY(hipEventCreate(&e1), "autotune: event");
   const int cells_c[] = {2, 4, 8, 16, 32, 64, 128};
-  double best = 1e300;
-  int bc = s->cells, bw = s->waves;
+  // time one shape: two untimed steps (they re-lay the partials and capture this shape's
+  // graph), then probe_steps timed graph replays
+  auto time_shape = [&](int ci, int wv, double* per) -> int {
+    s->cells = ci;
+    s->waves = wv;
+    int r = hrlb_step(s, 2);
+    if (r != HRLB_OK) return r;
+    hipError_t e = hipEventRecord(e0, s->stream);
+    if (e == hipSuccess) {
+      r = hrlb_step(s, probe_steps);
+      if (r != HRLB_OK) return r;
+      e = hipEventRecord(e1, s->stream);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) return hip_fail(e, "autotune: timing");
+    *per = ms / probe_steps;
+    return HRLB_OK;
+  };
+  struct Cand {
+    double per;
+    int cells, waves;
+  };
+  std::vector<Cand> cand;
   int rc = HRLB_OK;
-  for (int wv = 1; wv <= MAX_WAVES && rc == HRLB_OK; ++wv) {
+  for (int wv = 1; wv <= MAX_WAVES && rc == HRLB_OK; ++wv)
     for (int ci : cells_c) {
       if (ci > 2 * s->sh.S) continue;
-      s->cells = ci;
-      s->waves = wv;
-      rc = hrlb_step(s, 2);  // re-lays out the partials and captures the graph of this shape
+      double per = 0;
+      rc = time_shape(ci, wv, &per);
       if (rc != HRLB_OK) break;
-      hipError_t e = hipEventRecord(e0, s->stream);
-      if (e == hipSuccess) rc = hrlb_step(s, probe_steps);
-      if (rc != HRLB_OK) break;
-      if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        rc = hip_fail(e, "autotune: timing");
-        break;
-      }
-      const double per = ms / probe_steps;
-      if (per < best) {
-        best = per;
-        bc = ci;
-        bw = wv;
-      }
+      cand.push_back({per, ci, wv});
+    }
+  // a second timing of the three fastest, each keeping its better time, so one noisy probe
+  // does not decide
+  if (rc == HRLB_OK) {
+    std::sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) { return a.per < b.per; });
+    for (size_t k = 0; k < cand.size() && k < 3 && rc == HRLB_OK; ++k) {
+      double per = 0;
+      rc = time_shape(cand[k].cells, cand[k].waves, &per);
+      cand[k].per = std::min(cand[k].per, per);
     }
   }
+  double best = 1e300;
+  int bc = s->cells, bw = s->waves;
+  for (const Cand& c2 : cand)
+    if (c2.per < best) {
+      best = c2.per;
+      bc = c2.cells;
+      bw = c2.waves;
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   s->cells = bc;
