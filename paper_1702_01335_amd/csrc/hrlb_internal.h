@@ -15,7 +15,7 @@ constexpr int QX_MAX = 128;
 constexpr int REC_HEAD = 16;  // scalars at the head of a per-node closure record
 constexpr int PART_STRIDE = 16;  // doubles per (block, node) moment partial: 13 moments, 3 zero
 constexpr int NMOM = 13;
-constexpr int MAX_WAVES = 4;   // waves per stage-kernel workgroup (LDS: ~10.4 KB per wave)
+constexpr int MAX_WAVES = 4;   // waves per stage-kernel workgroup (LDS: 8.3 KB per wave, 12.4 KB with several)
 // 64-velocity blocks of the moment-multiplier table: those of V, plus the whole idle waves
 // a workgroup of up to MAX_WAVES waves can hold past V
 constexpr int ptab_blocks(int V) { return (V + 63) / 64 + MAX_WAVES - 1; }

@@ -411,9 +411,9 @@ __device__ __forceinline__ void store_moments(const dbl4& acc, const double* lds
 }
 
 // LDS of the stage and partials kernels (doubles): the waves' node tiles, then (blocks of
-// several waves) the parked contractions, then two residual sums per wave
+// several waves) two buffers of parked contractions, then two residual sums per wave
 __host__ __device__ inline int lds_red_offset(int waves) { return waves * FT_WAVE; }
-__host__ __device__ inline int lds_res_offset(int waves) { return waves * FT_WAVE + (waves > 1 ? waves * RED_WAVE : 0); }
+__host__ __device__ inline int lds_res_offset(int waves) { return waves * FT_WAVE + (waves > 1 ? 2 * waves * RED_WAVE : 0); }
 
 __global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, const double* __restrict__ F, int nvb,
                                                        int nch, int cs) {
@@ -891,8 +891,7 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   }
   ld_sc(s0, sc[0]);
 
-  int last_cnt = 0, last_g = 0;
-  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  dbl4 acc;
   // the contraction's A operands (the multipliers of the wave's 64 velocities) stay in
   // registers for the whole tile: eight 16-byte loads once instead of per group
   double pa[16];
@@ -917,26 +916,24 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
       ld_near(c + PIPE, near[u % PIPE]);
     }
     // Stores happen only here, once per 16 nodes: the group's results from the lane's own
-    // LDS column and the previous group's moment sums, right before the contraction waits
-    // for its operands.  Loads and stores share one counter, so any wait issued while a
-    // store is in flight drains everything; with the stores bunched here that single drain
-    // covers them and the prefetched loads together, and the march starts each group
-    // with no store outstanding, so its waits stay partial.
+    // LDS column, then its moment sums.  Loads and stores share one counter, so a wait
+    // issued while a store is in flight drains everything; with the stores bunched here
+    // the march starts each group with its next operands already loaded.  Blocks of several
+    // waves add their contractions in LDS, in one of two buffers taken in turn, so a single
+    // barrier per group orders the parking and the summing (a wave cannot get a whole
+    // group ahead of the others); blocks of one wave need no barrier.
     if (active) {
       auto dst = gmem(Fout + base + (size_t)(s0 + g) * V + v);
       for (int u = 0; u < cnt; ++u) dst[(size_t)u * V] = ft[u * FT_LD + lane];
     }
-    if (g > 0) store_moments(acc, lds_red, waves, 16, part + (size_t)(g - 16) * nstride, nstride);
-    __syncthreads();
     acc = moment_mfma(lds_ft + wave * FT_WAVE, pa, lane);
+    double* red = lds_red + ((g >> 4) & 1) * waves * RED_WAVE;
     if (waves > 1) {
-      park_moments(lds_red, acc, wave, lane);
+      park_moments(red, acc, wave, lane);
+      __syncthreads();
     }
-    __syncthreads();
-    last_cnt = cnt;
-    last_g = g;
+    store_moments(acc, red, waves, cnt, part + (size_t)g * nstride, nstride);
   }
-  store_moments(acc, lds_red, waves, last_cnt, part + (size_t)last_g * nstride, nstride);
   if constexpr (STAGE == 3) {
     rd = wave_sum(rd);
     rf = wave_sum(rf);
