@@ -23,6 +23,12 @@ SMALL = [
     ('linear5-shakhov', make_wl(5, 4, 3, 13, 'linear5', A=0.5, dt=1e-4)),
     ('upwind2-lowmach', make_wl(4, 2, 1, 10, 'upwind2', pr=1.0, law='lowmach', kn=0.5, u_w=1e-5, dt=2e-3)),
     ('weno5-lowmach', make_wl(7, 2, 1, 12, 'weno5', pr=1.0, law='lowmach', kn=0.05, u_w=1e-3, A=0.98, dt=1e-4)),
+    # degenerate sizes: the fewest nodes the three bounce-back images allow, a velocity set
+    # of two (one per x half, a wave with 62 idle lanes), exactly one wave of velocities
+    ('minimal-S3', make_wl(2, 2, 2, 3, 'weno5', pr=1.0)),
+    ('shakhov-S3', make_wl(3, 4, 4, 3, 'weno5', dt=1e-4)),
+    ('tiny-V2', make_wl(1, 1, 1, 5, 'upwind2', pr=1.0)),
+    ('one-wave-V64', make_wl(4, 4, 2, 7, 'linear5', A=0.5, dt=1e-4)),
 ]
 
 
