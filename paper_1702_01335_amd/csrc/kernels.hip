@@ -995,7 +995,7 @@ __global__ void __launch_bounds__(64) batch_closure_kernel(const GroupDesc* __re
   closure_block(g.sh, g.d, g.d.F[stage - 1], g.nvb, nullptr, it.y, g.node_blocks, g.nb, cl_lds);
 }
 
-__global__ void __launch_bounds__(256) residual_kernel(Shape sh, DevPtrs d, int nres) {
+__global__ void __launch_bounds__(256) residual_kernel(DevPtrs d, int nres) {
   const int b = blockIdx.x;
   __shared__ double r0[256], r1[256];
   double a = 0.0, f = 0.0;
@@ -1096,7 +1096,7 @@ int launch_stage(const Shape& sh, const DevPtrs& d, int stage, const double* Fin
 }
 
 int launch_residual(const Shape& sh, const DevPtrs& d, int nres, void* stream) {
-  hipLaunchKernelGGL(residual_kernel, dim3(sh.B), dim3(256), 0, (hipStream_t)stream, sh, d, nres);
+  hipLaunchKernelGGL(residual_kernel, dim3(sh.B), dim3(256), 0, (hipStream_t)stream, d, nres);
   return (int)hipGetLastError();
 }
 
