@@ -110,7 +110,7 @@ def sweep_section(n_inst, n_steady, steps):
     """Ragged sweep measurements.  Throughput: n_inst instances drawn from the sweep
     distribution (kn log-uniform in [0.01, 100], u_w in [0.05, 0.6], omega in
     {0.5, 0.72, 0.81, 1}, Qx in {4, 8, 16, 32}, S in {64, 128, 256}, Qy = Qz = 5, upwind2)
-    advanced as one autotuned persistent batch, against the same groups stepped one after
+    advanced as one autotuned batch, against the same groups stepped one after
     another and against every instance stepped alone.  Time to steady state: n_steady
     instances of the same distribution restricted to S = 64 and Qx in {4, 8}, run to
     residual 1e-10 as one batch that retires converged instances, against the same

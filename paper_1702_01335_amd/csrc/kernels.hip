@@ -519,28 +519,26 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
   const int nblk_nodes = min(nb, total - g0);
   // Every load of a phase is issued before any of its results is used: the block's time
   // is a chain of memory round trips, so each phase should cost one.
-  // 0) the projection tables (and the half-range monomial coefficients) into LDS
-  {
-    const int n1 = nphx, n2 = n1 + nphy, n3 = n2 + nphz, n4 = n3 + ncx;
-    for (int e0 = lane; e0 < n4; e0 += 256) {
-      double x[4];
+  // 0) the projection tables (and the half-range monomial coefficients) into LDS.  The
+  //    first 256 entries (all of them for Qx <= 28 at N = 6) are loaded into registers here
+  //    and written to LDS only after the partial sums below, so their loads overlap
+  //    those of the sums instead of costing a round trip of their own.
+  const int n1 = nphx, n2 = n1 + nphy, n3 = n2 + nphz, n4 = n3 + ncx;
+  auto table_entry = [&](int e) -> double {
+    return (e < n1)   ? gmem(d.phix)[e]
+           : (e < n2) ? gmem(d.phiy)[e - n1]
+           : (e < n3) ? gmem(d.phiz)[e - n2]
+           : (e < n4) ? gmem(d.cx)[e - n3]
+                      : 0.0;
+  };
+  auto table_store = [&](int e, double x) {
+    if (e < n3) phix[e] = x;  // phix, phiy, phiz are contiguous in LDS
+    else if (e < n4) cxl[e - n3] = x;
+  };
+  double tab[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int e = e0 + 64 * k;
-        x[k] = (e < n1)   ? gmem(d.phix)[e]
-               : (e < n2) ? gmem(d.phiy)[e - n1]
-               : (e < n3) ? gmem(d.phiz)[e - n2]
-               : (e < n4) ? gmem(d.cx)[e - n3]
-                          : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int e = e0 + 64 * k;
-        if (e < n3) phix[e] = x[k];  // phix, phiy, phiz are contiguous in LDS
-        else if (e < n4) cxl[e - n3] = x[k];
-      }
-    }
-  }
+  for (int k = 0; k < 4; ++k) tab[k] = table_entry(lane + 64 * k);
+  for (int e0 = lane + 256; e0 < n4; e0 += 64) table_store(e0, table_entry(e0));
   // 1) sum the moment partials over velocity blocks.  They are node-major ([node][nvb][16]),
   //    so the block's nodes are one contiguous range; lane l owns moment l % 16 of nodes
   //    l / 16 + 4 j and sums four velocity blocks per pass for all of them at once
@@ -568,6 +566,8 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
       }
     }
   }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) table_store(lane + 64 * k, tab[k]);
   __syncthreads();
   // 2) one lane per node: moments, tau, Shakhov coefficients, projection coefficients
   const bool live = lane < nblk_nodes;
@@ -659,18 +659,30 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
     gyz[nd * Qyz + e] = (e < sh.Qy) ? full_node(phiy, sh.Ny, e, sn + oay) : full_node(phiz, sh.Nz, e - sh.Qy, sn + oaz);
   }
   __syncthreads();
+  // (node, entry) of lane l advance by 64 entries per pass without a division; the pair
+  // (j, k) of a g_y g_z entry comes from a float reciprocal, corrected to the exact quotient
   const int nx2 = 2 * sh.Qx, E = nx2 + sh.QyQz;
-  for (int idx = lane; idx < nblk_nodes * E; idx += 64) {
-    const int nd = idx / E, e = idx - nd * E;
+  const float inv_qz = 1.0f / (float)sh.Qz;
+  int nd = lane / E, e = lane - nd * E;
+  while (nd < nblk_nodes) {
     double val;
     if (e < nx2) {
       const double* sn = scal + nd * SC;
       val = gx_node(phix, sh.Qx, sh.Nx, e, sn, sn + oJm);
     } else {
-      const int jk = e - nx2, j = jk / sh.Qz, k = jk - j * sh.Qz;
+      const int jk = e - nx2;
+      int j = (int)((float)jk * inv_qz);
+      if (j * sh.Qz > jk) --j;
+      if ((j + 1) * sh.Qz <= jk) ++j;
+      const int k = jk - j * sh.Qz;
       val = gyz[nd * Qyz + j] * gyz[nd * Qyz + sh.Qy + k];
     }
     gmem(d.rec)[(size_t)(g0 + nd) * sh.rec_len + REC_HEAD + e] = val;
+    e += 64;
+    while (e >= E) {
+      e -= E;
+      ++nd;
+    }
   }
 }
 
