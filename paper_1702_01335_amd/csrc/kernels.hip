@@ -328,11 +328,11 @@ __global__ void clear_flags_kernel(int* flags, int n) {
 // moment partials on the matrix cores
 //
 // The 13 moment sums of a node over a wave's 64 velocities are a dense contraction over
-// the velocity axis: D[m][n] = sum_v P[v][m] F[n][v] for 16 nodes n at a time, with
+// the velocity axis: D[n][m] = sum_v F[n][v] P[v][m] for 16 nodes n at a time, with
 // P[v][.] = {1, p_x, p_y, p_z, p_x^2, p_y^2, p_z^2, p_x p_y, p_x p_z, p_y p_z,
 // |p|^2 p_x, |p|^2 p_y, |p|^2 p_z, 0, 0, 0}.  Each wave parks the 16 node rows of F it has
 // produced in LDS and issues 16 v_mfma_f64_16x16x4 (K = 4 velocities each); the
-// operand layouts are A[m][k] in lane m + 16k, B[k][n] in lane n + 16k, and
+// operand layouts are A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, and
 // D[4r + l/16][l % 16] in lane l, result register r (checked on gfx950).
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -355,19 +355,24 @@ __device__ __forceinline__ void load_moment_operands(const double* __restrict__ 
   }
 }
 
+// D[node][moment] = sum_v F[v][node] P[moment][v] over the wave's 64 velocities, in 16
+// steps of 4: the node tile is the A operand (lane l: node l % 16, velocity 4 t + l / 16)
+// and the multipliers the B operand (lane l: velocity 4 t + l / 16, moment l % 16), so
+// register r of lane l ends up holding moment l % 16 of node 4 r + l / 16
 __device__ __forceinline__ dbl4 moment_mfma(const double* ft, const double* a, int lane) {
   dbl4 acc = {0.0, 0.0, 0.0, 0.0};
   const int n = lane & 15, kk = lane >> 4;
 #pragma unroll
-  for (int t = 0; t < 16; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], ft[n * FT_LD + 4 * t + kk], acc, 0, 0, 0);
+  for (int t = 0; t < 16; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ft[n * FT_LD + 4 * t + kk], a[t], acc, 0, 0, 0);
   return acc;
 }
 
 // Moment sums of a group of 16 node rows, once every wave has stored its rows in its tile:
 // the wave contracts its tile with the multipliers of its 64 velocities on the matrix
-// cores (A operands loaded here; the stage kernel keeps them in registers instead); the 13
-// sums of node n end up in the lanes that hold D[.][n].  A block of one wave stores them
-// straight from these registers; with more waves they are added across waves in LDS first.
+// cores (the multipliers loaded here; the stage kernel keeps them in registers instead);
+// the 13 sums of node n end up in the lanes that hold D[n][.].  A block of one wave stores
+// them straight from these registers; with more waves they are added across waves in LDS
+// first.
 __device__ __forceinline__ dbl4 moment_contract(const double* lds_ft, const double* __restrict__ ptab, int wave_v0,
                                                 int V, int wave, int lane) {
   double a[16];
@@ -378,28 +383,27 @@ __device__ __forceinline__ dbl4 moment_contract(const double* lds_ft, const doub
 
 // park a wave's contraction in lds_red[wave][node][16] (blocks of several waves)
 __device__ __forceinline__ void park_moments(double* lds_red, const dbl4& acc, int wave, int lane) {
-  double* r = lds_red + wave * RED_WAVE + (lane & 15) * 16 + (lane >> 4);
+  double* r = lds_red + wave * RED_WAVE + (lane >> 4) * 16 + (lane & 15);
   r[0] = acc[0];
-  r[4] = acc[1];
-  r[8] = acc[2];
-  r[12] = acc[3];
+  r[64] = acc[1];
+  r[128] = acc[2];
+  r[192] = acc[3];
 }
 
 // store the moment sums of cnt nodes, node-major with node_stride: from the registers of a
-// one-wave block (register r of lane l holds moment 4 r + l / 16 of node l % 16), or from
+// one-wave block (register r of lane l holds moment l % 16 of node 4 r + l / 16), or from
 // the waves' parked contractions summed in LDS.  All 16 slots of a node's row are written
-// (the contraction leaves slots 13..15 zero), so each row is one whole 128-byte line: rows
-// written in part cost measurably more.
+// (the contraction leaves slots 13..15 zero), and one store instruction writes four whole
+// 128-byte rows: rows written in part, or a line in several pieces, cost measurably more.
 __device__ __forceinline__ void store_moments(const dbl4& acc, const double* lds_red, int waves, int cnt,
                                               double* __restrict__ out, int node_stride) {
   if (waves == 1) {
-    const int lane = threadIdx.x, n = lane & 15, m0 = lane >> 4;
-    if (n < cnt) {
-      auto o = gmem(out + (size_t)n * node_stride + m0);
+    const int lane = threadIdx.x, q = lane & 15, n0 = lane >> 4;
+    auto o = gmem(out + (size_t)n0 * node_stride + q);
+    const size_t step = (size_t)4 * node_stride;
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        o[4 * r] = acc[r];
-    }
+    for (int r = 0; r < 4; ++r)
+      if (4 * r + n0 < cnt) o[r * step] = acc[r];
     return;
   }
   for (int idx = threadIdx.x; idx < cnt * PART_STRIDE; idx += blockDim.x) {
@@ -904,7 +908,7 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   ld_sc(s0, sc[0]);
 
   dbl4 acc;
-  // the contraction's A operands (the multipliers of the wave's 64 velocities) stay in
+  // the contraction's B operands (the multipliers of the wave's 64 velocities) stay in
   // registers for the whole tile: eight 16-byte loads once instead of per group
   double pa[16];
   load_moment_operands(d.ptab, wave_v0, V, lane, pa);
