@@ -899,13 +899,12 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   };
   Far far[PIPE];
   Near near[PIPE];
-  Sc sc[2];
+  Sc sc;
 #pragma unroll
   for (int k = 0; k < PIPE; ++k) {
     ld_far(s0 + k, far[k]);
     ld_near(s0 + k, near[k]);
   }
-  ld_sc(s0, sc[0]);
 
   dbl4 acc;
   // the contraction's B operands (the multipliers of the wave's 64 velocities) stay in
@@ -922,8 +921,8 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int c = s0 + g + u;
-      ld_sc(c, sc[0]);
-      const double out = node(c, far[u % PIPE], near[u % PIPE], sc[0], u < cnt);
+      ld_sc(c, sc);
+      const double out = node(c, far[u % PIPE], near[u % PIPE], sc, u < cnt);
       ft[u * FT_LD + lane] = out;
       // the prefetches are issued on every path (clamped addresses): a load under a branch
       // would have to be merged into one register at the join, and that copy would wait
