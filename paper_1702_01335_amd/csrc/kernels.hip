@@ -522,7 +522,15 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
   const int g0 = blk * nb;
   const int nblk_nodes = min(nb, total - g0);
   // Every load of a phase is issued before any of its results is used: the block's time
-  // is a chain of memory round trips, so each phase should cost one.
+  // is a chain of memory round trips, so each phase should cost one.  The parameters of
+  // each lane's node (its instance's collision law, dt, and 1 / dx of the node) are loaded
+  // first, so that they arrive with the partial sums.
+  const bool live = lane < nblk_nodes;
+  const int g = g0 + (live ? lane : 0), b = g / S;
+  const auto in = gmem(d.inst + b);
+  const double p_law = in->law, p_kn = in->kn, p_om = in->omega, p_su = in->suth;
+  const double p_cl = in->collisionless, p_pr = in->pr, p_dt = in->dt;
+  const double p_idx = gmem(d.inv_dx)[g];
   // 0) the projection tables (and the half-range monomial coefficients) into LDS.  The
   //    first 256 entries (all of them for Qx <= 28 at N = 6) are loaded into registers here
   //    and written to LDS only after the partial sums below, so their loads overlap
@@ -573,12 +581,10 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
 #pragma unroll
   for (int k = 0; k < 4; ++k) table_store(lane + 64 * k, tab[k]);
   __syncthreads();
-  // 2) one lane per node: moments, tau, Shakhov coefficients, projection coefficients
-  const bool live = lane < nblk_nodes;
-  const int g = g0 + (live ? lane : 0), b = g / S, c = g - b * S;
-  (void)c;
-  const auto in = gmem(d.inst + b);
-  const double* M = msum + lane * PART_STRIDE;
+  // 2) one lane per node: moments, tau, Shakhov coefficients, full-range projection
+  //    coefficients; n, u_x and T go to the three spare slots of the node's sum row
+  static_assert(PART_STRIDE >= NMOM + 3, "the sum row carries n, u_x and T after the moments");
+  double* M = msum + (live ? lane : 0) * PART_STRIDE;
   const double n = live ? M[0] : 1.0;
   const double ux = live ? M[1] / n : 0.0, uy = live ? M[2] / n : 0.0, uz = live ? M[3] / n : 0.0;
   const double Pxx = M[4] - n * ux * ux, Pyy = M[5] - n * uy * uy, Pzz = M[6] - n * uz * uz;
@@ -613,38 +619,31 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
     if (bad) gmem(d.flags)[b] = 1;
     // relaxation time from mu = tau n T
     double tau;
-    if (in->law == 0.0)
-      tau = in->kn * pow(T, in->omega - 1.0) / n;
-    else if (in->law == 1.0)
-      tau = in->kn * (1.0 + in->suth) / (n * sqrt(T) * (1.0 + in->suth / T));
+    if (p_law == 0.0)
+      tau = p_kn * pow(T, p_om - 1.0) / n;
+    else if (p_law == 1.0)
+      tau = p_kn * (1.0 + p_su) / (n * sqrt(T) * (1.0 + p_su / T));
     else
-      tau = in->kn * M_SQRT1_2;  // linearised (low Mach) regime, Eq. knLuo: tau = k / sqrt(2)
-    const double invtau = (in->collisionless != 0.0 || bad) ? 0.0 : 1.0 / tau;
-    const double Cs = (1.0 - in->pr) / (n * T * T);
+      tau = p_kn * M_SQRT1_2;  // linearised (low Mach) regime, Eq. knLuo: tau = k / sqrt(2)
+    const double invtau = (p_cl != 0.0 || bad) ? 0.0 : 1.0 / tau;
+    const double Cs = (1.0 - p_pr) / (n * T * T);
     const auto rec = gmem(d.rec + (size_t)g * sh.rec_len);
     rec[0] = ux;
     rec[1] = uy;
     rec[2] = uz;
-    rec[3] = in->dt * invtau;
+    rec[3] = p_dt * invtau;
     rec[4] = Cs;
     rec[5] = Cs / (5.0 * T);
     rec[6] = qx;
     rec[7] = qy;
     rec[8] = qz;
-    rec[9] = in->dt * gmem(d.inv_dx)[g];
+    rec[9] = p_dt * p_idx;
     // projection coefficients of the 1D Maxwellian factors (Sec. III)
-    double I[NX_MAX + 1], J[NX_MAX + 1], a[NYZ_MAX + 1];
+    double a[NYZ_MAX + 1];
     const double Tc = bad ? 1.0 : T;
-    half_gauss_moments(ux, Tc, I);
-    half_projection(cxl, sh.Nx, I, J);
-#pragma unroll
-    for (int l = 0; l <= NX_MAX; ++l)
-      if (l <= sh.Nx) sc[l] = n * J[l];
-    half_gauss_moments(-ux, Tc, I);
-    half_projection(cxl, sh.Nx, I, J);
-#pragma unroll
-    for (int l = 0; l <= NX_MAX; ++l)
-      if (l <= sh.Nx) sc[oJm + l] = n * J[l];
+    M[NMOM] = n;
+    M[NMOM + 1] = ux;
+    M[NMOM + 2] = Tc;
     full_coeffs(uy, Tc, a);
 #pragma unroll
     for (int l = 0; l <= NYZ_MAX; ++l)
@@ -655,37 +654,64 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
       if (l <= sh.Nz) sc[oaz + l] = a[l];
   }
   __syncthreads();
-  // 3) g_y and g_z of every node of the block, then the coalesced fill of the equilibrium
-  //    tables: n g_x on the 2Qx nodes and g_y g_z on the QyQz pairs
+  // 3) the half-range projection coefficients n J^+ and n J^-, one lane per node and
+  //    semi-axis (the two share one pass through the exponential and erfc), and g_y and g_z
+  //    of every node of the block
+  //    (at most 2 x 64 tasks; straight-line passes, since in a loop the compiler would hold
+  //    the constants of erfc in registers across it)
+  static_assert(CL_NODES <= 64, "two passes cover every (node, semi-axis) task");
+  auto half_pair = [&](int t) {
+    if (t < 2 * nblk_nodes) {
+      const int nd = t >> 1;
+      const double* R = msum + nd * PART_STRIDE;
+      double I[NX_MAX + 1], J[NX_MAX + 1];
+      half_gauss_moments((t & 1) ? -R[NMOM + 1] : R[NMOM + 1], R[NMOM + 2], I);
+      half_projection(cxl, sh.Nx, I, J);
+      double* o = scal + nd * SC + ((t & 1) ? oJm : 0);
+#pragma unroll
+      for (int l = 0; l <= NX_MAX; ++l)
+        if (l <= sh.Nx) o[l] = R[NMOM] * J[l];
+    }
+  };
+  half_pair(lane);
+  if (nblk_nodes > 32) half_pair(lane + 64);
   for (int idx = lane; idx < nblk_nodes * Qyz; idx += 64) {
     const int nd = idx / Qyz, e = idx - nd * Qyz;
     const double* sn = scal + nd * SC;
     gyz[nd * Qyz + e] = (e < sh.Qy) ? full_node(phiy, sh.Ny, e, sn + oay) : full_node(phiz, sh.Nz, e - sh.Qy, sn + oaz);
   }
   __syncthreads();
-  // (node, entry) of lane l advance by 64 entries per pass without a division; the pair
-  // (j, k) of a g_y g_z entry comes from a float reciprocal, corrected to the exact quotient
-  const int nx2 = 2 * sh.Qx, E = nx2 + sh.QyQz;
-  const float inv_qz = 1.0f / (float)sh.Qz;
-  int nd = lane / E, e = lane - nd * E;
-  while (nd < nblk_nodes) {
-    double val;
-    if (e < nx2) {
+  // 4) the coalesced fill of the equilibrium tables, n g_x on the 2Qx nodes, then g_y g_z on
+  //    the QyQz pairs (two loops, so that no pass mixes the two kinds of entry).  (node, entry)
+  //    of lane l advance by 64 entries per pass without a division; the pair (j, k) of a
+  //    g_y g_z entry comes from a float reciprocal, corrected to the exact quotient
+  const int nx2 = 2 * sh.Qx, QyQz = sh.QyQz;
+  {
+    int nd = lane / nx2, e = lane - nd * nx2;
+    while (nd < nblk_nodes) {
       const double* sn = scal + nd * SC;
-      val = gx_node(phix, sh.Qx, sh.Nx, e, sn, sn + oJm);
-    } else {
-      const int jk = e - nx2;
+      gmem(d.rec)[(size_t)(g0 + nd) * sh.rec_len + REC_HEAD + e] = gx_node(phix, sh.Qx, sh.Nx, e, sn, sn + oJm);
+      e += 64;
+      while (e >= nx2) {
+        e -= nx2;
+        ++nd;
+      }
+    }
+  }
+  {
+    const float inv_qz = 1.0f / (float)sh.Qz;
+    int nd = lane / QyQz, jk = lane - nd * QyQz;
+    while (nd < nblk_nodes) {
       int j = (int)((float)jk * inv_qz);
       if (j * sh.Qz > jk) --j;
       if ((j + 1) * sh.Qz <= jk) ++j;
       const int k = jk - j * sh.Qz;
-      val = gyz[nd * Qyz + j] * gyz[nd * Qyz + sh.Qy + k];
-    }
-    gmem(d.rec)[(size_t)(g0 + nd) * sh.rec_len + REC_HEAD + e] = val;
-    e += 64;
-    while (e >= E) {
-      e -= E;
-      ++nd;
+      gmem(d.rec)[(size_t)(g0 + nd) * sh.rec_len + REC_HEAD + nx2 + jk] = gyz[nd * Qyz + j] * gyz[nd * Qyz + sh.Qy + k];
+      jk += 64;
+      while (jk >= QyQz) {
+        jk -= QyQz;
+        ++nd;
+      }
     }
   }
 }
