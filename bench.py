@@ -103,7 +103,7 @@ def profiled_traffic(tag, bytes_per_launch, cells, waves):
         return None
     ks = tr['stage_kernels'].values()
     t = sum(k['fetch_bytes'] + k['write_bytes'] for k in ks) / len(ks)
-    return {'bytes_per_launch': t, 'over_algorithmic': t / bytes_per_launch, 'source': f'profiles/{tag}.md'}
+    return {'bytes_per_launch': t, 'over_algorithmic': t / bytes_per_launch, 'source': f'profiles/{tag}_c{cells}w{waves}.md'}
 
 
 def sweep_section(n_inst, n_steady, steps):
