@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import solver as sv
+from paper_1702_01335_amd import hrlb, inputs
 from paper_1702_01335_amd.workloads import workload
 
 from parity import assert_parity, gpu_run, make_wl, oracle_run
@@ -75,6 +76,41 @@ def test_batch_of_different_instances():
         Fo, m, Ro = oracle_run(base, 4, seed=21 + b, params=p)
         assert_parity(Fg[b], Fo, m, f"instance {b}")
         assert res[b] == pytest.approx(Ro, rel=1e-9)
+
+
+def test_closure_blocks_of_64_nodes():
+    """Enough nodes (1100 instances x 250) that the closure takes 64 nodes per block, so the
+    half-range projections need their second pass of (node, semi-axis) tasks; 250 is not a
+    multiple of 64, so blocks straddle instances, and the last block holds 56 nodes.  Every
+    instance has its own parameters; a sample, the last one included, must match the
+    oracle."""
+    base = make_wl(3, 4, 4, 250, 'weno5', dt=2e-4)
+    B = 1100
+    plist = []
+    for b in range(B):
+        p = dict(base['params'], u_w=0.1 + 0.4 * (b % 7) / 6, kn=0.05 * 1.5 ** (b % 9), omega=0.5 + 0.1 * (b % 6))
+        if b % 5 == 3:
+            p.update(law='sutherland', suth_S=0.5239)
+        plist.append(p)
+    seeds = list(range(4000, 4000 + B))
+    Fg, _, res, _ = gpu_run(base, 3, seeds=seeds, params_list=plist, launch=(64, 1))
+    for b in (0, 1, 3, 511, 1098, 1099):
+        Fo, m, Ro = oracle_run(base, 3, seed=4000 + b, params=plist[b])
+        assert_parity(Fg[b], Fo, m, f"instance {b} of {B}")
+        assert res[b] == pytest.approx(Ro, rel=1e-9)
+    # the same instances as a one-group batch: its closure items take 64 nodes too (32 would
+    # need more items than blocks can be resident); same launch shape, so the same sums
+    import torch
+    q = hrlb.Quadrature(3, 4, 4)
+    r = torch.from_numpy(np.stack([inputs.perturbation(sd, (250, q.V)) for sd in seeds])).cuda()
+    s = hrlb.Solver(q, 250, 'weno5', [hrlb.make_params(**p) for p in plist], perturb=r, eps=0.05)
+    bt = hrlb.Batch([s], 64, 1)
+    bt.step(3)
+    Fb = s.get_state().cpu().numpy()
+    err = np.abs(Fb - Fg).max() / np.abs(Fg).max()
+    print(f"[parity] batched 64-node closure items: max rel diff vs single-instance path {err:.2e}", flush=True)
+    assert err <= 1e-15
+    assert np.allclose(bt.residual(), res, rtol=1e-13)
 
 
 @pytest.mark.parametrize("steps", [1, 10, 60])
