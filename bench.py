@@ -174,7 +174,7 @@ def sweep_section(n_inst, n_steady, steps):
 
 
 def workloads_section(steps, warmup):
-    """Every workload at its own size: one instance (latency-bound: 0.5 to 118 MB per step)
+    """Every workload at its own size: one instance (latency-bound: 0.3 to 118 MB per step)
     and a batch large enough to live in HBM rather than in the 256 MB last-level cache.
     Launch shapes autotuned, HIP graph on."""
     import torch
@@ -182,7 +182,8 @@ def workloads_section(steps, warmup):
     out = []
     for name, batch in (('couette_bgk_s64_v128', 1), ('couette_bgk_s64_v128', 4096),
                         ('couette_shakhov_s256_v800', 1), ('couette_shakhov_s256_v800', 512),
-                        ('couette_shakhov_s512_v3600', 1), ('couette_shakhov_s512_v3600', 64)):
+                        ('couette_shakhov_s512_v3600', 1), ('couette_shakhov_s512_v3600', 64),
+                        ('paper_maxwell_s16_v686', 1), ('paper_maxwell_s16_v686', 4096)):
         wl = workload(name)
         q, s = make_solver(wl, batch, 'cuda:0')
         c, w, _ = s.autotune(probe_steps=3)

@@ -131,6 +131,17 @@ def test_shakhov_s256_v800_full_size(steps):
     assert res[0] == pytest.approx(Ro, rel=1e-8)
 
 
+@pytest.mark.parametrize("steps", [1, 20])
+def test_paper_maxwell_s16_v686_full_size(steps):
+    """The paper's own shape (Sec. V runs): 16 stretched nodes, HHLB(6;7) x HLB(6;7) x
+    HLB(6;7), WENO-5, dt = 5e-4."""
+    wl = workload('paper_maxwell_s16_v686')
+    Fg, _, res, _ = gpu_run(wl, steps, seeds=[5])
+    Fo, m, Ro = oracle_run(wl, steps, seed=5)
+    assert_parity(Fg[0], Fo, m, f"paper maxwell s16 v686 steps={steps}")
+    assert res[0] == pytest.approx(Ro, rel=1e-8)
+
+
 def test_shakhov_s512_v3600_full_size():
     wl = workload('couette_shakhov_s512_v3600')
     Fg, _, res, _ = gpu_run(wl, 2, seeds=[3])
