@@ -454,8 +454,8 @@ __global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, cons
 }
 
 // ---------------------------------------------------------------------------------------
-// closure: 64 nodes per block (one lane per node for the scalar closure), plus one wall
-// block per instance
+// closure: up to 64 nodes per block (one lane per node for the scalar closure, one per node
+// and semi-axis for the half-range projections), plus one wall block per instance
 
 
 // one closure work item: node block `blk` (< node_blocks) or the wall of instance
