@@ -246,7 +246,7 @@ def cpu_baseline(wl, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({'error': 'this build runs on one GPU only; multi-GPU runs are not part of it',
+        print(json.dumps({'error': 'one GPU only: the library drives a single device and has no multi-GPU path',
                           'n_gpus': args.gpus}))
         sys.exit(2)
     import torch
