@@ -131,6 +131,32 @@ def test_shakhov_s256_v800_full_size(steps):
     assert res[0] == pytest.approx(Ro, rel=1e-8)
 
 
+@pytest.mark.parametrize("cells,waves", [(64, 1), (64, 2), (32, 1), (32, 2)])
+def test_bench_configuration_sampled_instances(cells, waves):
+    """The configuration the benchmark times: 256 instances of couette_shakhov_s256_v800,
+    seeded as the benchmark seeds them (splitmix64 streams 1000 + b, eps = 0.05), in each
+    launch shape the autotuner picks, with the step captured in a HIP graph.  Sampled
+    instances (first, middle, last) must match the oracle run from the same input."""
+    import torch
+    wl = workload('couette_shakhov_s256_v800')
+    B, S, steps = 256, wl['S'], 3
+    q = hrlb.Quadrature(wl['Qx'], wl['Qy'], wl['Qz'])
+    r = torch.from_numpy(np.stack([inputs.perturbation(1000 + b, (S, q.V)) for b in range(B)])).cuda()
+    s = hrlb.Solver(q, S, wl['scheme'], [hrlb.make_params(**wl['params'])] * B, perturb=r, eps=0.05)
+    del r
+    s.set_launch(cells, waves)
+    s.set_graph(True)
+    s.step(steps)
+    res = s.residual()
+    F = s.get_state()
+    for b in (0, 127, 255):
+        Fo, m, Ro = oracle_run(wl, steps, seed=1000 + b)
+        assert_parity(F[b].cpu().numpy(), Fo, m, f"bench configuration {cells}x{waves}, instance {b}")
+        assert res[b] == pytest.approx(Ro, rel=1e-8)
+    del F, s
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("steps", [1, 20])
 def test_paper_maxwell_s16_v686_full_size(steps):
     """The paper's own shape (Sec. V runs): 16 stretched nodes, HHLB(6;7) x HLB(6;7) x
