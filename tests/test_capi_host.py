@@ -114,6 +114,18 @@ def test_init_state_rejects_small_buffers_and_bad_shapes():
     assert e.value.code == hrlb.HRLB_EINVAL
 
 
+def test_empty_batch_is_rejected():
+    """A batch of no instances is an argument error, reported before any device use."""
+    q = hrlb.Quadrature(4, 4, 4)
+    with pytest.raises(hrlb.HrlbError) as e:
+        hrlb.state_bytes(q.handle, 8, 0)
+    assert e.value.code == hrlb.HRLB_EINVAL
+    sb, wb = hrlb.state_bytes(q.handle, 8, 1)
+    with pytest.raises(hrlb.HrlbError) as e:
+        hrlb.init_state(q.handle, 8, 0, [], FakeBuf(1 << 20, sb), FakeBuf(1 << 30, wb), 0)
+    assert e.value.code == hrlb.HRLB_EINVAL
+
+
 def test_mlp_sizes_and_argument_checks():
     lib = network.load()
     sb, wb = ctypes.c_size_t(), ctypes.c_size_t()

@@ -176,6 +176,20 @@ def test_shakhov_s512_v3600_full_size():
     assert res[0] == pytest.approx(Ro, rel=1e-8)
 
 
+def test_zero_steps_leave_the_state_unchanged():
+    """nsteps = 0 enqueues nothing, eager or graph-captured, single or batched."""
+    wl = make_wl(5, 3, 3, 12, 'weno5')
+    _, _, _, s = gpu_run(wl, 2, seeds=[31, 32], params_list=[wl['params']] * 2)
+    F0 = s.get_state().cpu().numpy()
+    for graph in (False, True):
+        s.set_graph(graph)
+        s.step(0)
+        assert np.array_equal(s.get_state().cpu().numpy(), F0)
+    bt = hrlb.Batch([s], 4, 1)
+    bt.step(0)
+    assert np.array_equal(s.get_state().cpu().numpy(), F0)
+
+
 def test_gas_at_rest_on_gpu():
     wl = make_wl(6, 5, 5, 20, 'weno5', u_w=0.0, A=0.98, dt=1e-4)
     Fg, mom, res, solver = gpu_run(wl, 200)
