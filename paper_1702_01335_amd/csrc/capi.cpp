@@ -536,7 +536,7 @@ int hrlb_autotune(hrlb_sim* s, int probe_steps, const char* cache_path, int* bes
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0), "autotune: event");
   HIP_TRY(hipEventCreate(&e1), "autotune: event");
-  const int cells_c[] = {2, 4, 8, 16, 32, 64, 128};
+  const int cells_c[] = {2, 4, 8, 16, 32, 48, 64, 96, 128};
   // time one shape: two untimed steps (they re-lay the partials and capture this shape's
   // graph), then probe_steps timed graph replays
   auto time_shape = [&](int ci, int wv, double* per) -> int {
