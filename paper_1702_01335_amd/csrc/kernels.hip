@@ -766,6 +766,13 @@ __device__ __forceinline__ double ld_buf(__amdgpu_buffer_rsrc_t r, unsigned lane
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, row_off, 0));
 }
 
+// the same load marked nontemporal (cache-policy operand 2: the nt bit), for the streams a
+// launch reads once: the caches then keep the node records and moment partials, which are
+// read again
+__device__ __forceinline__ double ld_buf_nt(__amdgpu_buffer_rsrc_t r, unsigned lane_off, unsigned row_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, row_off, 2));
+}
+
 // complete a node beyond the wall (App. A.4): p_x > 0 by quadratic extrapolation from the
 // three nodes below (f1 nearest), p_x < 0 the wall Maxwellian n_w F^eq_w; nodes past
 // the third ghost are never read.  The extrapolation weights (uniform) are read by scalar
@@ -837,8 +844,8 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
 
   // Per-node operands, software-pipelined in rotating register sets (the node loop is
   // unrolled by PIPE, so no register with a load in flight is ever copied).  The two HBM
-  // streams, the window node c+3 and F_l, and the two equilibrium-factor gathers (which hit
-  // the cache) run PIPE nodes ahead.  All are unconditional vector loads with clamped
+  // streams, the window node c+3 and F_l (nontemporal loads), and the two equilibrium-factor
+  // gathers (which hit the cache) run PIPE nodes ahead.  All are unconditional vector loads with clamped
   // addresses, which complete in order; each is a wave-uniform row offset in a scalar
   // register plus a fixed 32-bit lane offset, so no address arithmetic is repeated per lane
   // and node.  The node's closure scalars are uniform and come by scalar loads (ld_sc).
@@ -862,9 +869,9 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   const unsigned row8 = 8u * V, rec8 = 8u * sh.rec_len;
   auto ld_far = [&](int c, Far& o) {
     // c + 3 >= 3 on the march: never a bounce-back image
-    o.raw = ld_buf(r_in, vv8, row8 * min(c + 3, S - 1));
+    o.raw = ld_buf_nt(r_in, vv8, row8 * min(c + 3, S - 1));
     if constexpr (STAGE != 1)
-      o.fl0 = ld_buf(r_l, vv8, row8 * min(c, clast));
+      o.fl0 = ld_buf_nt(r_l, vv8, row8 * min(c, clast));
     else
       o.fl0 = 0.0;
   };
@@ -962,10 +969,14 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
     // the march starts each group with its next operands already loaded.  Blocks of several
     // waves add their contractions in LDS, in one of two buffers taken in turn, so a single
     // barrier per group orders the parking and the summing (a wave cannot get a whole
-    // group ahead of the others); blocks of one wave need no barrier.
+    // group ahead of the others); blocks of one wave need no barrier.  The rows are stored
+    // nontemporal, as the two streams are loaded: the next launch reads them back at the
+    // earliest, and a batch's arrays outgrow the last-level cache, which then keeps the
+    // moment partials and node records that the closure and the next stage read (measured:
+    // 5-8 % off stage and closure together).
     if (active) {
       auto dst = gmem(Fout + base + (size_t)(s0 + g) * V + v);
-      for (int u = 0; u < cnt; ++u) dst[(size_t)u * V] = ft[u * FT_LD + lane];
+      for (int u = 0; u < cnt; ++u) __builtin_nontemporal_store(ft[u * FT_LD + lane], &dst[(size_t)u * V]);
     }
     acc = moment_mfma(lds_ft + wave * FT_WAVE, pa, lane);
     double* red = lds_red + ((g >> 4) & 1) * waves * RED_WAVE;
