@@ -553,7 +553,8 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
   for (int e0 = lane + 256; e0 < n4; e0 += 64) table_store(e0, table_entry(e0));
   // 1) sum the moment partials over velocity blocks.  They are node-major ([node][nvb][16]),
   //    so the block's nodes are one contiguous range; lane l owns moment l % 16 of nodes
-  //    l / 16 + 4 j and sums four velocity blocks per pass for all of them at once
+  //    l / 16 + 4 j and sums four velocity blocks per pass for all of them at once.  Each
+  //    partial is read once, so the loads are nontemporal
   {
     const int q = lane & 15, n0 = lane >> 4;
     for (int j0 = 0; j0 < nb; j0 += 16) {
@@ -566,7 +567,8 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
           const bool ok = nd < nblk_nodes && q < NMOM;
           const auto src = gmem(d.partials + ((size_t)(g0 + (ok ? nd : 0)) * nvb) * PART_STRIDE + q);
 #pragma unroll
-          for (int t = 0; t < 4; ++t) x[j][t] = (ok && vb0 + t < nvb) ? src[(size_t)(vb0 + t) * PART_STRIDE] : 0.0;
+          for (int t = 0; t < 4; ++t)
+            x[j][t] = (ok && vb0 + t < nvb) ? __builtin_nontemporal_load(&src[(size_t)(vb0 + t) * PART_STRIDE]) : 0.0;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[j] += (x[j][0] + x[j][1]) + (x[j][2] + x[j][3]);
