@@ -80,10 +80,11 @@ class Sweep:
                 tot += d['S'] * 2 * d['Qx'] * self.QyQz
         return tot
 
-    def autotune(self, cells=(4, 8, 16, 32, 64), waves=(1, 2, 4), probe_steps=10):
+    def autotune(self, cells=(4, 8, 16, 32, 64), waves=(1, 2, 4), probe_steps=10, active=None):
         """Time probe_steps batched steps for each (cells, waves) candidate, keep the fastest
-        as self.batch and put every group's state back where it was.  Returns
-        (cells, waves, ms per step)."""
+        as self.batch and put every group's state back where it was.  active (batch order),
+        if given, holds the instances still stepping: the probes time only those, and the
+        kept batch has the same set active.  Returns (cells, waves, ms per step)."""
         import torch
         saved = [g[2].get_state().clone() for g in self.groups]
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -91,6 +92,8 @@ class Sweep:
         for c in cells:
             for w in waves:
                 b = hrlb.Batch([g[2] for g in self.groups], c, w)
+                if active is not None:
+                    b.set_active(active)
                 b.step(2)
                 e0.record()
                 b.step(probe_steps)
@@ -104,19 +107,29 @@ class Sweep:
             g[2].set_state(F)
         self.cells, self.waves, ms = best
         self.batch = hrlb.Batch([g[2] for g in self.groups], self.cells, self.waves)
+        if active is not None:
+            self.batch.set_active(active)
         torch.cuda.synchronize()
         return self.cells, self.waves, ms
 
-    def run_to_steady(self, tol, max_steps, check_every=200, progress=None):
+    def run_to_steady(self, tol, max_steps, check_every=200, progress=None, retune=False):
         """Step until every instance's residual is below tol (retiring converged ones) or the
         step budget is spent.  Returns per-instance steps in batch order (-1 if not
-        converged), the final residuals and the wall time.  progress, if given, is called
-        after every residual check with (steps done, instances still active)."""
+        converged), the residuals (each retired instance's at its retirement, the others'
+        at the last check) and the wall time.  progress, if given, is called
+        after every residual check with (steps done, instances still active).  With retune,
+        the launch shape is timed again for the instances left whenever their number has
+        halved since the last tuning (a shape tuned for many instances leaves few tiles, and
+        long ones, to the last few); the tuning time counts in the wall time.  A new shape
+        sums in another order, so step counts can then differ from an untuned run's by a
+        residual check at the threshold."""
         steps = np.full(self.B, -1)
         active = np.ones(self.B, dtype=np.int32)
+        tuned_for = self.B
         done = 0
         t0 = time.perf_counter()
         R = np.full(self.B, np.inf)
+        R_out = np.full(self.B, np.inf)
         while done < max_steps and active.any():
             n = min(check_every, max_steps - done)
             self.batch.step(n)
@@ -125,13 +138,18 @@ class Sweep:
             newly = (R < tol) & (active == 1)
             if newly.any():
                 steps[newly] = done
+                R_out[newly] = R[newly]
                 active[newly] = 0
                 if active.any():
                     self.batch.set_active(active)
+                    if retune and active.sum() <= tuned_for // 2:
+                        self.autotune(cells=(8, 16, 32, 64), waves=(1, 2, 4), probe_steps=5, active=active)
+                        tuned_for = int(active.sum())
             if progress is not None:
                 progress(done, int(active.sum()))
         wall = time.perf_counter() - t0
-        return steps, R, wall
+        R_out[active == 1] = R[active == 1]
+        return steps, R_out, wall
 
     def run_plain(self, tol, max_steps, check_every=200):
         """The same instances, in batch order, each alone in its own Solver with a
@@ -188,7 +206,7 @@ def main():
             t_last[0] = time.perf_counter()
             print(json.dumps({'steps': done, 'active': n_active}), flush=True)
 
-    steps, R, wall = sw.run_to_steady(a.tol, a.max_steps, a.check_every, progress)
+    steps, R, wall = sw.run_to_steady(a.tol, a.max_steps, a.check_every, progress, retune=True)
     print(json.dumps({'batched_wall_s': wall, 'converged': int((steps > 0).sum())}), flush=True)
     # single-instance step time per shape
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -210,6 +228,7 @@ def main():
         n = steps[k] if steps[k] > 0 else a.max_steps
         plain += n * t_shape[(d['Qx'], d['S'])]
     res = dict(instances=a.instances, seed=a.seed, tol=a.tol, check_every=a.check_every, launch=[c, w],
+               final_launch=[sw.cells, sw.waves],
                converged=int((steps > 0).sum()), batched_wall_s=wall, plain_estimate_s=plain,
                speedup_estimate=plain / wall, steps_max=int(steps.max()), steps_median=float(np.median(steps)),
                single_step_ms={f"Qx{k[0]}_S{k[1]}": v * 1e3 for k, v in t_shape.items()},

@@ -111,6 +111,21 @@ def test_sweep_runs_to_steady_with_retirement():
     assert (R < 1e-8).all()
 
 
+def test_sweep_retunes_as_instances_retire():
+    """run_to_steady(retune=True) times the launch shape again each time the active set has
+    halved (the probes step only the active instances and the state is put back): every
+    instance still converges, within one residual check of the fixed-shape run."""
+    inst = sample(10, 20170204, kn_range=(0.3, 3.0), qx=(4,), nodes=(12, 16))
+    ref = Sweep(inst, Qy=4, Qz=4, scheme='upwind2', cells=4, waves=2)
+    s_ref, _, _ = ref.run_to_steady(tol=1e-8, max_steps=60000, check_every=500)
+    sw = Sweep(inst, Qy=4, Qz=4, scheme='upwind2', cells=4, waves=2)
+    steps, R, wall = sw.run_to_steady(tol=1e-8, max_steps=60000, check_every=500, retune=True)
+    print(f"[sweep] retuned: steps {steps.tolist()} (fixed shape {s_ref.tolist()}), final launch "
+          f"{sw.cells}x{sw.waves}, wall {wall:.2f}s", flush=True)
+    assert (steps > 0).all() and (R < 1e-8).all()
+    assert np.abs(steps - s_ref).max() <= 500
+
+
 def test_batches_sharing_sims_relayout_partials():
     """Two batches with different wave counts over the same sims, interleaved with a step of
     one sim alone: every switch re-lays the moment partials, so the result matches one
