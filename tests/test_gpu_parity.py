@@ -131,7 +131,7 @@ def test_shakhov_s256_v800_full_size(steps):
     assert res[0] == pytest.approx(Ro, rel=1e-8)
 
 
-@pytest.mark.parametrize("cells,waves", [(64, 1), (64, 2), (32, 1), (32, 2), (96, 1), (128, 1)])
+@pytest.mark.parametrize("cells,waves", [(64, 1), (64, 2), (32, 1), (32, 2), (96, 1), (128, 1), (48, 1), (48, 2)])
 def test_bench_configuration_sampled_instances(cells, waves):
     """The configuration the benchmark times: 256 instances of couette_shakhov_s256_v800,
     seeded as the benchmark seeds them (splitmix64 streams 1000 + b, eps = 0.05), in each
