@@ -239,6 +239,35 @@ int hrlb_batch_set_active(hrlb_batch* batch, const int* active);
 int hrlb_batch_info(const hrlb_batch* batch, int* ntiles, int* nitems, int* grid_stage, int* grid_closure);
 void hrlb_batch_free(hrlb_batch* batch);
 
+/*
+ * step_noalloc -- for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hrlb_init_state's tables,
+ * then `nsteps` RK3 steps as hrlb_step takes them, then optionally hrlb_moments, on the
+ * caller's populations, with every table, moment partial, closure record and flag in a fixed
+ * device array of HRLB_SCRATCH_BYTES that the library holds on each GPU it runs on until the
+ * process ends.  No hipMalloc, hipFree or other allocating device call is made.
+ *   q, S, scheme, params, batch: as for hrlb_init_state.
+ *   d_state: caller device buffer of hrlb_state_bytes' state size (256-byte aligned); its
+ *     first array [batch][S][V] holds F_l on entry and F_{l+nsteps} on return, the other
+ *     two are overwritten.
+ *   d_moments: NULL, or a device array [batch][S][14] that receives the moments of the
+ *     result in hrlb_moments' column order.
+ *   stream: hipStream_t everything is enqueued on.
+ * The launch shape is the library's default; the results equal those of hrlb_init_state,
+ * hrlb_set_state with the same populations, hrlb_step(nsteps) eagerly and hrlb_moments,
+ * bit for bit.  The call synchronises `stream` once, after uploading the tables (host
+ * staging), and leaves the steps enqueued.  Every call on one GPU uses that GPU's array,
+ * which keeps the last call's contents (flags and residuals are cleared at each call):
+ * calls that overlap on one GPU, on different streams or threads, race.  Numerical faults
+ * are not read back; a non-finite moment table shows them.
+ * Errors: HRLB_EINVAL (as hrlb_init_state, nsteps < 0), HRLB_ENOMEM (state buffer too small,
+ * or the batch needs more work memory than HRLB_SCRATCH_BYTES: hrlb_state_bytes' work
+ * size must not exceed it), HRLB_EHIP.
+ */
+#define HRLB_SCRATCH_BYTES ((size_t)32 << 20)
+int hrlb_step_noalloc(const hrlb_quad* q, int S, int scheme, const hrlb_params* params, int batch, void* d_state,
+                      size_t state_bytes, int nsteps, double* d_moments, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -237,56 +237,33 @@ int hrlb_state_bytes(const hrlb_quad* q, int S, int batch, size_t* state_bytes, 
   return HRLB_OK;
 }
 
-int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* params, int batch, void* d_state,
-                    size_t state_bytes, void* d_work, size_t work_bytes, void* stream, const double* d_perturb,
-                    double eps, hrlb_sim** out) {
-  if (!out) return fail(HRLB_EINVAL, "init_state: out is NULL");
-  *out = nullptr;
-  if (!q || !params || !d_state || !d_work) return fail(HRLB_EINVAL, "init_state: NULL argument");
-  if (S < 3) return fail(HRLB_EINVAL, "init_state: S must be >= 3 (three ghost layers mirror nodes 1..3)");
-  if (batch < 1) return fail(HRLB_EINVAL, "init_state: batch must be >= 1");
+// Parameter checks shared by init_state and step_noalloc (before any device use).
+static int check_instances(const char* fn, int S, int scheme, const hrlb_params* params, int batch) {
+  const std::string f(fn);
+  if (S < 3) return fail(HRLB_EINVAL, f + ": S must be >= 3 (three ghost layers mirror nodes 1..3)");
+  if (batch < 1) return fail(HRLB_EINVAL, f + ": batch must be >= 1");
   if (scheme != HRLB_SCHEME_UPWIND2 && scheme != HRLB_SCHEME_WENO5 && scheme != HRLB_SCHEME_LINEAR5)
-    return fail(HRLB_EINVAL, "init_state: unknown scheme");
-  if (((uintptr_t)d_state & 255) || ((uintptr_t)d_work & 255))
-    return fail(HRLB_EINVAL, "init_state: buffers must be 256-byte aligned");
+    return fail(HRLB_EINVAL, f + ": unknown scheme");
   for (int b = 0; b < batch; ++b) {
     const hrlb_params& p = params[b];
     const std::string at = " (instance " + std::to_string(b) + ")";
-    if (!(p.dt > 0) || !std::isfinite(p.dt)) return fail(HRLB_EINVAL, "init_state: dt must be > 0" + at);
-    if (!(p.kn > 0) || !std::isfinite(p.kn)) return fail(HRLB_EINVAL, "init_state: kn must be > 0" + at);
-    if (!(p.T_w > 0)) return fail(HRLB_EINVAL, "init_state: T_w must be > 0" + at);
-    if (!(p.n0 > 0)) return fail(HRLB_EINVAL, "init_state: n0 must be > 0" + at);
-    if (!(p.pr > 0)) return fail(HRLB_EINVAL, "init_state: pr must be > 0" + at);
-    if (!(p.A >= 0 && p.A < 1)) return fail(HRLB_EINVAL, "init_state: A must be in [0, 1)" + at);
+    if (!(p.dt > 0) || !std::isfinite(p.dt)) return fail(HRLB_EINVAL, f + ": dt must be > 0" + at);
+    if (!(p.kn > 0) || !std::isfinite(p.kn)) return fail(HRLB_EINVAL, f + ": kn must be > 0" + at);
+    if (!(p.T_w > 0)) return fail(HRLB_EINVAL, f + ": T_w must be > 0" + at);
+    if (!(p.n0 > 0)) return fail(HRLB_EINVAL, f + ": n0 must be > 0" + at);
+    if (!(p.pr > 0)) return fail(HRLB_EINVAL, f + ": pr must be > 0" + at);
+    if (!(p.A >= 0 && p.A < 1)) return fail(HRLB_EINVAL, f + ": A must be in [0, 1)" + at);
     if (p.law != HRLB_LAW_POWER && p.law != HRLB_LAW_SUTHERLAND && p.law != HRLB_LAW_LOWMACH)
-      return fail(HRLB_EINVAL, "init_state: unknown law" + at);
-    if (p.law == HRLB_LAW_SUTHERLAND && !(p.suth_S >= 0)) return fail(HRLB_EINVAL, "init_state: suth_S must be >= 0" + at);
-    if (!std::isfinite(p.u_w) || !std::isfinite(p.omega)) return fail(HRLB_EINVAL, "init_state: non-finite u_w/omega" + at);
+      return fail(HRLB_EINVAL, f + ": unknown law" + at);
+    if (p.law == HRLB_LAW_SUTHERLAND && !(p.suth_S >= 0)) return fail(HRLB_EINVAL, f + ": suth_S must be >= 0" + at);
+    if (!std::isfinite(p.u_w) || !std::isfinite(p.omega)) return fail(HRLB_EINVAL, f + ": non-finite u_w/omega" + at);
   }
-  const Shape sh = make_shape(q->t, S, batch, scheme);
-  if (!instance_fits(sh)) return fail(HRLB_EINVAL, "init_state: one instance's populations (S * V * 8 bytes) must stay below 4 GiB");
-  const WorkLayout L = work_layout(sh);
-  const size_t arr = align256((size_t)batch * S * sh.V * sizeof(double));
-  if (state_bytes < 3 * arr) return fail(HRLB_ENOMEM, "init_state: state buffer smaller than hrlb_state_bytes");
-  if (work_bytes < L.total) return fail(HRLB_ENOMEM, "init_state: work buffer smaller than hrlb_state_bytes");
+  return HRLB_OK;
+}
 
-  hrlb_sim* s = new hrlb_sim;
-  s->sh = sh;
-  s->lay = L;
-  s->stream = (hipStream_t)stream;
-  s->cells = default_cells(sh);
-  s->waves = default_waves(sh);
-  s->part_nvb = 0;
-  s->resid_nres = 0;
-  s->timing = false;
-  s->graph_on = false;
-  s->gexec = nullptr;
-  s->cap_stream = nullptr;
-  s->g_cells = s->g_waves = 0;
-  s->ms[0] = s->ms[1] = 0;
-  s->launches[0] = s->launches[1] = 0;
-  char* w = (char*)d_work;
-  DevPtrs& d = s->d;
+// Device pointers of a work region laid out by L and of the three population arrays.
+static DevPtrs carve(const WorkLayout& L, char* w, char* state, size_t arr) {
+  DevPtrs d;
   d.px = (const double*)(w + L.px);
   d.py = (const double*)(w + L.py);
   d.pz = (const double*)(w + L.pz);
@@ -306,9 +283,17 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
   d.resid = (double*)(w + L.resid);
   d.flags = (int*)(w + L.flags);
   d.junk = (double*)(w + L.junk);
-  for (int k = 0; k < 3; ++k) d.F[k] = (double*)((char*)d_state + k * arr);
+  for (int k = 0; k < 3; ++k) d.F[k] = (double*)(state + k * arr);
+  return d;
+}
 
-  // host-side per-instance tables
+// Upload the velocity-set tables and the per-instance constants (collision parameters,
+// Lagrange weights of the wall extrapolation, 1/dx of every node) on st, clear the fault
+// flags and residuals with a fill kernel, and synchronise st (the host staging vectors die
+// on return).  Then fill the equilibrium tables on the device.
+static hipError_t upload_tables(const QuadTables& t, const Shape& sh, const hrlb_params* params, const DevPtrs& d,
+                                hipStream_t st) {
+  const int batch = sh.B, S = sh.S;
   std::vector<InstDev> inst(batch);
   std::vector<double> invdx((size_t)batch * S);
   for (int b = 0; b < batch; ++b) {
@@ -338,8 +323,6 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
       invdx[(size_t)b * S + c] = 1.0 / dx;
     }
   }
-  hipStream_t st = s->stream;
-  const QuadTables& t = q->t;
   auto up = [&](const void* dst, const void* src, size_t bytes) {
     return hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, st);
   };
@@ -353,22 +336,104 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
   if (e == hipSuccess) e = up(d.phiz, t.phiz.data(), t.phiz.size() * sizeof(double));
   if (e == hipSuccess) e = up(d.inst, inst.data(), inst.size() * sizeof(InstDev));
   if (e == hipSuccess) e = up(d.inv_dx, invdx.data(), invdx.size() * sizeof(double));
-  if (e == hipSuccess) e = hipMemsetAsync(d.flags, 0, batch * sizeof(int), st);
-  if (e == hipSuccess) e = hipMemsetAsync(d.resid, 0, batch * sizeof(double), st);
+  if (e == hipSuccess) e = (hipError_t)launch_clear_flags(sh, d, st);
   // the host vectors above must stay alive until the copies complete
   if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = (hipError_t)launch_setup_tables(sh, d, st);
+  return e;
+}
+
+int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* params, int batch, void* d_state,
+                    size_t state_bytes, void* d_work, size_t work_bytes, void* stream, const double* d_perturb,
+                    double eps, hrlb_sim** out) {
+  if (!out) return fail(HRLB_EINVAL, "init_state: out is NULL");
+  *out = nullptr;
+  if (!q || !params || !d_state || !d_work) return fail(HRLB_EINVAL, "init_state: NULL argument");
+  int rc = check_instances("init_state", S, scheme, params, batch);
+  if (rc != HRLB_OK) return rc;
+  if (((uintptr_t)d_state & 255) || ((uintptr_t)d_work & 255))
+    return fail(HRLB_EINVAL, "init_state: buffers must be 256-byte aligned");
+  const Shape sh = make_shape(q->t, S, batch, scheme);
+  if (!instance_fits(sh)) return fail(HRLB_EINVAL, "init_state: one instance's populations (S * V * 8 bytes) must stay below 4 GiB");
+  const WorkLayout L = work_layout(sh);
+  const size_t arr = align256((size_t)batch * S * sh.V * sizeof(double));
+  if (state_bytes < 3 * arr) return fail(HRLB_ENOMEM, "init_state: state buffer smaller than hrlb_state_bytes");
+  if (work_bytes < L.total) return fail(HRLB_ENOMEM, "init_state: work buffer smaller than hrlb_state_bytes");
+
+  hrlb_sim* s = new hrlb_sim;
+  s->sh = sh;
+  s->lay = L;
+  s->stream = (hipStream_t)stream;
+  s->cells = default_cells(sh);
+  s->waves = default_waves(sh);
+  s->part_nvb = 0;
+  s->resid_nres = 0;
+  s->timing = false;
+  s->graph_on = false;
+  s->gexec = nullptr;
+  s->cap_stream = nullptr;
+  s->g_cells = s->g_waves = 0;
+  s->ms[0] = s->ms[1] = 0;
+  s->launches[0] = s->launches[1] = 0;
+  s->d = carve(L, (char*)d_work, (char*)d_state, arr);
+  const DevPtrs& d = s->d;
+  hipStream_t st = s->stream;
+  hipError_t e = upload_tables(q->t, sh, params, d, st);
   if (e != hipSuccess) {
     delete s;
     return hip_fail(e, "init_state: table upload");
   }
-  if ((e = (hipError_t)launch_setup_tables(sh, d, st)) != hipSuccess ||
-      (e = (hipError_t)launch_init_state(sh, d, d_perturb, eps, st)) != hipSuccess ||
+  if ((e = (hipError_t)launch_init_state(sh, d, d_perturb, eps, st)) != hipSuccess ||
       (e = (hipError_t)launch_partials(sh, d, d.F[0], s->cells, s->waves, st)) != hipSuccess) {
     delete s;
     return hip_fail(e, "init_state: launch");
   }
   s->part_nvb = (sh.V + 64 * s->waves - 1) / (64 * s->waves);
   *out = s;
+  return HRLB_OK;
+}
+
+int hrlb_step_noalloc(const hrlb_quad* q, int S, int scheme, const hrlb_params* params, int batch, void* d_state,
+                      size_t state_bytes, int nsteps, double* d_moments, void* stream) {
+  if (!q || !params || !d_state) return fail(HRLB_EINVAL, "step_noalloc: NULL argument");
+  if (nsteps < 0) return fail(HRLB_EINVAL, "step_noalloc: nsteps must be >= 0");
+  int rc = check_instances("step_noalloc", S, scheme, params, batch);
+  if (rc != HRLB_OK) return rc;
+  if ((uintptr_t)d_state & 255) return fail(HRLB_EINVAL, "step_noalloc: state buffer must be 256-byte aligned");
+  const Shape sh = make_shape(q->t, S, batch, scheme);
+  if (!instance_fits(sh))
+    return fail(HRLB_EINVAL, "step_noalloc: one instance's populations (S * V * 8 bytes) must stay below 4 GiB");
+  const WorkLayout L = work_layout(sh);
+  if (L.total > SCRATCH_BYTES)
+    return fail(HRLB_ENOMEM, "step_noalloc: this batch needs " + std::to_string(L.total) +
+                                 " bytes of work memory, more than the fixed array's " + std::to_string(SCRATCH_BYTES) +
+                                 " (HRLB_SCRATCH_BYTES); use hrlb_init_state with a work buffer, or fewer instances");
+  const size_t arr = align256((size_t)batch * S * sh.V * sizeof(double));
+  if (state_bytes < 3 * arr) return fail(HRLB_ENOMEM, "step_noalloc: state buffer smaller than hrlb_state_bytes");
+  void* work = nullptr;
+  hipError_t e = (hipError_t)scratch_pointer(&work);
+  if (e != hipSuccess) return hip_fail(e, "step_noalloc: address of the fixed work array");
+  const DevPtrs d = carve(L, (char*)work, (char*)d_state, arr);
+  hipStream_t st = (hipStream_t)stream;
+  e = upload_tables(q->t, sh, params, d, st);
+  if (e != hipSuccess) return hip_fail(e, "step_noalloc: table upload");
+  // the launch sequence of hrlb_init_state (partials of the current state) and of the eager
+  // hrlb_step with the default launch shape, so the results equal that path's
+  const int cells = default_cells(sh), waves = default_waves(sh);
+  const int nvb = (sh.V + 64 * waves - 1) / (64 * waves);
+  e = (hipError_t)launch_partials(sh, d, d.F[0], cells, waves, st);
+  for (int n = 0; n < nsteps && e == hipSuccess; ++n)
+    for (int stage = 1; stage <= 3 && e == hipSuccess; ++stage) {
+      const double* Fin = d.F[stage - 1];
+      double* Fout = d.F[stage % 3];
+      e = (hipError_t)launch_closure(sh, d, Fin, nvb, nullptr, st);
+      if (e == hipSuccess) e = (hipError_t)launch_stage(sh, d, stage, Fin, d.F[0], Fout, cells, waves, st);
+    }
+  if (e == hipSuccess && d_moments) {
+    e = (hipError_t)launch_partials(sh, d, d.F[0], cells, waves, st);
+    if (e == hipSuccess) e = (hipError_t)launch_closure(sh, d, d.F[0], nvb, d_moments, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "step_noalloc: launch");
   return HRLB_OK;
 }
 

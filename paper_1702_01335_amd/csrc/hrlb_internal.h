@@ -124,4 +124,10 @@ constexpr int CL_NODES = 64;  // most nodes per closure block
 int closure_nodes_for(int total_nodes);
 int batch_closure_blocks_per_cu(size_t lds_bytes);  // resident batch-closure blocks per CU
 
+// bytes of the fixed per-GPU work array of hrlb_step_noalloc (HRLB_SCRATCH_BYTES in hrlb.h)
+constexpr size_t SCRATCH_BYTES = (size_t)32 << 20;
+// device address of that array on the current device (looked up once per device); returns
+// a hipError_t cast to int
+int scratch_pointer(void** out);
+
 }  // namespace hrlb

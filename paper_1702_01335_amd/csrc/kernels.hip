@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "hrlb_internal.h"
 
@@ -319,9 +320,14 @@ __global__ void __launch_bounds__(256) seed_kernel(Shape sh, DevPtrs d, const do
   }
 }
 
-__global__ void clear_flags_kernel(int* flags, int n) {
+// fault flags and residuals of every instance to zero (a fill kernel rather than a memset,
+// so a caller's graph capture records no memset node)
+__global__ void clear_flags_kernel(int* flags, double* resid, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) flags[i] = 0;
+  if (i < n) {
+    flags[i] = 0;
+    resid[i] = 0.0;
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1099,7 +1105,8 @@ int launch_seed(const Shape& sh, const DevPtrs& d, const double* tab, int preser
 }
 
 int launch_clear_flags(const Shape& sh, const DevPtrs& d, void* stream) {
-  hipLaunchKernelGGL(clear_flags_kernel, dim3((sh.B + 255) / 256), dim3(256), 0, (hipStream_t)stream, d.flags, sh.B);
+  hipLaunchKernelGGL(clear_flags_kernel, dim3((sh.B + 255) / 256), dim3(256), 0, (hipStream_t)stream, d.flags, d.resid,
+                     sh.B);
   return (int)hipGetLastError();
 }
 
@@ -1184,6 +1191,34 @@ int launch_batch_closure(int stage, const GroupDesc* groups, const void* items, 
   hipLaunchKernelGGL(batch_closure_kernel, dim3(grid), dim3(64), lds_bytes, (hipStream_t)stream, groups,
                      (const int2*)items, nitems, stage);
   return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// fixed work memory of hrlb_step_noalloc, for callers that cannot allocate device memory:
+// one array per GPU, held until the process ends.  In host code the name `scratch` is a
+// host-side stand-in, not a device address; every host use goes through the address that
+// hipGetSymbolAddress returns for the current device (each GPU has its own copy at its own
+// address), taken once per device and kept.
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+int scratch_pointer(void** out) {
+  constexpr int MAX_DEVICES = 64;
+  static std::mutex mu;
+  static void* ptr[MAX_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  if (dev < 0 || dev >= MAX_DEVICES) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    if (!p) return (int)hipErrorInvalidSymbol;
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return (int)hipSuccess;
 }
 
 }  // namespace hrlb

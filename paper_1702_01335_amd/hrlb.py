@@ -24,7 +24,9 @@ EXPORTS = ('hrlb_last_error', 'hrlb_init_quadrature', 'hrlb_quad_free', 'hrlb_qu
            'hrlb_state_bytes', 'hrlb_init_state', 'hrlb_sim_free', 'hrlb_step', 'hrlb_moments', 'hrlb_residual',
            'hrlb_get_state', 'hrlb_set_state', 'hrlb_set_launch', 'hrlb_get_launch', 'hrlb_autotune', 'hrlb_set_graph',
            'hrlb_set_timing', 'hrlb_get_timing', 'hrlb_batch_bytes', 'hrlb_batch_create', 'hrlb_batch_step',
-           'hrlb_batch_residual', 'hrlb_batch_set_active', 'hrlb_batch_info', 'hrlb_batch_free', 'hrlb_seed_state')
+           'hrlb_batch_residual', 'hrlb_batch_set_active', 'hrlb_batch_info', 'hrlb_batch_free', 'hrlb_seed_state',
+           'hrlb_step_noalloc')
+SCRATCH_BYTES = 32 << 20  # HRLB_SCRATCH_BYTES
 
 
 class HrlbError(RuntimeError):
@@ -95,6 +97,8 @@ def load():
     lib.hrlb_batch_info.argtypes = [vp, ip, ip, ip, ip]
     lib.hrlb_batch_free.argtypes = [vp]
     lib.hrlb_batch_free.restype = None
+    lib.hrlb_step_noalloc.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Params), ctypes.c_int, vp, sz,
+                                      ctypes.c_int, vp, vp]
     for name in EXPORTS:
         if name not in ('hrlb_last_error', 'hrlb_quad_free', 'hrlb_sim_free', 'hrlb_batch_free'):
             getattr(lib, name).restype = ctypes.c_int
@@ -138,6 +142,17 @@ def step(sim, nsteps):
 
 def moments(sim, out):
     _check(load().hrlb_moments(sim, ctypes.c_void_p(out.data_ptr())))
+
+
+def step_noalloc(quad, S, scheme, params, state, nsteps, moments_out, stream):
+    """hrlb_step_noalloc: state is a device uint8 tensor of the state size; its first
+    [B][S][V] float64 array is advanced in place; moments_out is None or a device float64
+    tensor [B][S][14]."""
+    arr = (Params * len(params))(*params)
+    _check(load().hrlb_step_noalloc(quad, S, scheme, arr, len(params), ctypes.c_void_p(state.data_ptr()),
+                                    state.numel(), nsteps,
+                                    ctypes.c_void_p(moments_out.data_ptr() if moments_out is not None else 0),
+                                    ctypes.c_void_p(stream)))
 
 
 def residual(sim, batch):

@@ -173,3 +173,28 @@ def test_instance_of_four_gib_is_rejected():
         hrlb.init_state(q.handle, 8192, 0, [p], FakeBuf(1 << 20, 1 << 45), FakeBuf(1 << 30, 1 << 40), 0)
     assert e.value.code == hrlb.HRLB_EINVAL
     assert '4 GiB' in str(e.value)
+
+
+def test_step_noalloc_checks_arguments_before_device_use():
+    """The fixed-array entry point rejects a batch whose work memory exceeds
+    HRLB_SCRATCH_BYTES (with the sizes in the message), a negative step count, bad
+    parameters and a small state buffer, all before any device use."""
+    q = hrlb.Quadrature(16, 5, 5)
+    p = hrlb.make_params(kn=1.0, dt=1e-5, pr=2 / 3, omega=0.5, u_w=0.4)
+    sb, wb = hrlb.state_bytes(q.handle, 256, 64)
+    assert wb > hrlb.SCRATCH_BYTES
+    with pytest.raises(hrlb.HrlbError) as e:
+        hrlb.step_noalloc(q.handle, 256, 1, [p] * 64, FakeBuf(1 << 20, sb), 1, None, 0)
+    assert e.value.code == hrlb.HRLB_ENOMEM and 'HRLB_SCRATCH_BYTES' in str(e.value)
+    sb, wb = hrlb.state_bytes(q.handle, 256, 2)
+    assert wb <= hrlb.SCRATCH_BYTES
+    with pytest.raises(hrlb.HrlbError) as e:
+        hrlb.step_noalloc(q.handle, 256, 1, [p] * 2, FakeBuf(1 << 20, sb), -1, None, 0)
+    assert e.value.code == hrlb.HRLB_EINVAL
+    with pytest.raises(hrlb.HrlbError) as e:
+        hrlb.step_noalloc(q.handle, 256, 1, [p] * 2, FakeBuf(1 << 20, sb - 8), 1, None, 0)
+    assert e.value.code == hrlb.HRLB_ENOMEM
+    bad = hrlb.make_params(kn=1.0, dt=0.0)
+    with pytest.raises(hrlb.HrlbError) as e:
+        hrlb.step_noalloc(q.handle, 256, 1, [p, bad], FakeBuf(1 << 20, sb), 1, None, 0)
+    assert e.value.code == hrlb.HRLB_EINVAL
