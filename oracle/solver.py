@@ -359,3 +359,72 @@ def run_to_steady(F, m: Model, tol, max_steps, check_every=100):
         if R < tol:
             break
     return F, steps, R
+
+
+class TwoWallModel:
+    """Test-only mode: the whole channel -L/2 <= x <= L/2 in 2S equidistant nodes, a diffuse
+    wall on each side (x = -L/2 moving with -u_w, x = +L/2 with +u_w, both at T_w), and no
+    centre line.  The paper solves only the half channel, with bounce-back at x = 0 standing
+    in for the other half by the symmetry of the flow (App. A.4); this mode exists to check
+    that symmetry.  Each wall is treated as App. A.4 treats the wall at L/2: outgoing
+    populations extrapolated quadratically into the ghost nodes, incoming ones the wall
+    Maxwellian with the density that makes the net mass flux through the wall vanish.
+    ``p.S`` is the node count of a half channel; ``p.A`` must be 0."""
+
+    def __init__(self, p: Params):
+        if p.A != 0.0:
+            raise ValueError("the two-wall mode uses the equidistant grid")
+        self.p = p
+        self.vs = VelocitySet(p.Qx, p.Qy, p.Qz, p.Nx, p.Ny, p.Nz)
+        self.V = self.vs.V
+        self.N = 2 * p.S
+        self.dx = np.full(self.N, 1.0 / self.N)
+        self.pos = self.vs.px > 0
+        self.neg = self.vs.px < 0
+        self.g_right = self.vs.maxwellian(1.0, 0.0, p.u_w, 0.0, p.T_w)
+        self.g_left = self.vs.maxwellian(1.0, 0.0, -p.u_w, 0.0, p.T_w)
+        self.den_right = np.sum(self.vs.px[self.neg] * self.g_right[self.neg])
+        self.den_left = np.sum(self.vs.px[self.pos] * self.g_left[self.pos])
+        x = lambda s: -0.5 + (s - 0.5) / self.N   # node s (1-based), ghosts continue the map
+
+        def lagrange(xs, x1, x2, x3):
+            return ((xs - x2) * (xs - x3) / ((x1 - x2) * (x1 - x3)),
+                    (xs - x1) * (xs - x3) / ((x2 - x1) * (x2 - x3)),
+                    (xs - x1) * (xs - x2) / ((x3 - x1) * (x3 - x2)))
+        N = self.N
+        # ghost t from the three nodes on its inner side, nearest first
+        self.ex_right = {t: lagrange(x(t), x(t - 1), x(t - 2), x(t - 3)) for t in (N + 1, N + 2)}
+        self.ex_left = {t: lagrange(x(t), x(t + 1), x(t + 2), x(t + 3)) for t in (0, -1)}
+
+
+def rhs_two_walls(F, m: TwoWallModel):
+    """L[F] of Eq. L_def on the whole channel (F has 2S rows); returns (L, n_w left, n_w right)."""
+    p, N, V = m.p, m.N, m.V
+    G = np.full((N + 6, V), np.nan)      # G[t + 2] = node t, t = -2 .. N+3
+    G[3:N + 3] = F
+    pos, neg = m.pos, m.neg
+    for t in (N + 1, N + 2):             # outgoing at the right wall: p_x > 0
+        c1, c2, c3 = m.ex_right[t]
+        G[t + 2, pos] = c1 * G[t + 1, pos] + c2 * G[t, pos] + c3 * G[t - 1, pos]
+    for t in (0, -1):                    # outgoing at the left wall: p_x < 0
+        c1, c2, c3 = m.ex_left[t]
+        G[t + 2, neg] = c1 * G[t + 3, neg] + c2 * G[t + 4, neg] + c3 * G[t + 5, neg]
+    phi_r = stencil_fluxes(G[:, pos], m.vs.px[pos], p.scheme, N, N)[0]
+    n_r = -np.sum(phi_r) / m.den_right
+    phi_l = stencil_fluxes(G[:, neg], m.vs.px[neg], p.scheme, 0, 0)[0]
+    n_l = -np.sum(phi_l) / m.den_left
+    for t in (N + 1, N + 2, N + 3):
+        G[t + 2, neg] = n_r * m.g_right[neg]
+    for t in (0, -1, -2):
+        G[t + 2, pos] = n_l * m.g_left[pos]
+    phi = stencil_fluxes(G, m.vs.px, p.scheme, 0, N)
+    D = (phi[1:] - phi[:-1]) / m.dx[:, None]
+    if p.collisionless:
+        return -D, n_l, n_r
+    mom = moments(F, m)
+    tau = relaxation_time(mom.n, mom.T, p)
+    return -D - (F - shakhov_target(mom, m)) / tau[:, None], n_l, n_r
+
+
+def rk3_step_two_walls(F, m: TwoWallModel):
+    return rk3(F, lambda G: rhs_two_walls(G, m)[0], m.p.dt)
