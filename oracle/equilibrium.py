@@ -63,6 +63,43 @@ def gaussian_moments(kmax, u, T):
     return out
 
 
+def _two_sum(a, b):
+    """s + e = a + b exactly (Knuth's TwoSum)."""
+    s = a + b
+    bb = s - a
+    return s, (a - (s - bb)) + (b - bb)
+
+
+def _two_prod(a, b):
+    """p + e = a b exactly (Dekker's TwoProduct with Veltkamp's splitting into 26-bit halves)."""
+    p = a * b
+
+    def split(x):
+        c = 134217729.0 * x
+        hi = c - (c - x)
+        return hi, x - hi
+    ah, al = split(a)
+    bh, bl = split(b)
+    return p, ((ah * bh - p) + ah * bl + al * bh) + al * bl
+
+
+def compensated_dot(C, m):
+    """J[..., l] = sum_k C[l, k] m[..., k] for every row l of C, each by Dot2 (Ogita, Rump and
+    Oishi, SIAM J. Sci. Comput. 26 (2005)): exact products and exact two-term sums over
+    k = 0, 1, ..., the rounding errors accumulated on the side, so the result is as accurate
+    as a dot product carried out in twice the working precision.  The projection
+    coefficients need it: J_l = sum_k C_lk I_k cancels (at rest it vanishes for l >= 1 while
+    its terms reach 1e3), and the outer half-range nodes multiply what is left by up to 1e7
+    (Qx = 50), so a plain sum's rounding would be the largest error of the equilibrium there.
+    (C is lower triangular; its zero entries add exact zeros.)"""
+    h, r = _two_prod(C, m[..., None, :])          # (..., l, k)
+    p, s = h[..., 0], r[..., 0]
+    for k in range(1, C.shape[1]):
+        p, q = _two_sum(p, h[..., k])
+        s = s + (q + r[..., k])
+    return p + s
+
+
 def monic_coefficients(a, b, N, dps):
     """Monomial coefficients C[l, k] of the monic orthogonal P_l (l <= N) and their norms
     gamma_l = b_0 b_1 ... b_l, from the recurrence P_{l+1} = (p - a_l) P_l - b_l P_{l-1}."""
@@ -104,6 +141,7 @@ class AxisProjection:
             # Phi[i, l] = w_i P_l(x_i) / gamma_l on the rule's own nodes
             Phi = [[w[i] * mp.fsum(C[l][k] * x[i] ** k for k in range(l + 1)) / gam[l]
                     for l in range(N + 1)] for i in range(Q)]
+        self._mp = (x, w, C, gam, dps)
         self.C = np.array([[float(v) for v in row] for row in C])  # (N+1, N+1)
         self.Phi = np.array([[float(v) for v in row] for row in Phi])  # (Q, N+1)
         if kind == 'half':
@@ -119,12 +157,57 @@ class AxisProjection:
             J = gaussian_moments(self.N, u, T) @ self.C.T           # J_l = sum_k C_lk E[X^k]
             return J @ self.Phi.T
         # positive semi-axis: J+_l = int_0^inf G(p) P_l(p) dp = sum_k C_lk I_k(u, T)
-        Jp = half_gaussian_moments(self.N, u, T) @ self.C.T
         # negative semi-axis, node -x_i: J-_l = int_0^inf G(-p) P_l(p) dp = sum_k C_lk I_k(-u, T)
-        Jm = half_gaussian_moments(self.N, -u, T) @ self.C.T
+        # (compensated sums over k <= l: see compensated_dot)
+        Ip = half_gaussian_moments(self.N, u, T)
+        Im = half_gaussian_moments(self.N, -u, T)
+        Jp = compensated_dot(self.C, Ip)
+        Jm = compensated_dot(self.C, Im)
         gp = Jp @ self.Phi.T            # nodes x_1 .. x_Q (ascending)
         gm = (Jm @ self.Phi.T)[..., ::-1]  # nodes -x_Q .. -x_1 (ascending)
         return np.concatenate([gm, gp], axis=-1)
+
+
+    def factor_exact(self, u, T):
+        """The same discrete factor g_i(u, T) for scalar u, T, evaluated in mpmath at the rule's
+        working precision from the rule's own (unrounded) nodes, weights and polynomials, and
+        rounded once to float64: the reference the float64 evaluations are measured against
+        (their error is the rounding of J_l = sum_k C_lk M_k amplified by P_l at the outer
+        nodes, which reaches 1e-9 relative at Qx = 50)."""
+        x, w, C, gam, dps = self._mp
+        N = self.N
+        with mp.workdps(dps):
+            u, T = mp.mpf(u), mp.mpf(T)
+
+            def moments(uu):
+                # I_k (half) or E[X^k] (full) for X ~ N(uu, T), k <= N, by the recursions of
+                # half_gaussian_moments / gaussian_moments, in mpmath
+                m = [mp.mpf(0)] * (N + 1)
+                if self.kind == 'half':
+                    m[0] = mp.erfc(-uu / mp.sqrt(2 * T)) / 2
+                    if N >= 1:
+                        m[1] = uu * m[0] + T * mp.exp(-uu * uu / (2 * T)) / mp.sqrt(2 * mp.pi * T)
+                else:
+                    m[0] = mp.mpf(1)
+                    if N >= 1:
+                        m[1] = uu
+                for k in range(2, N + 1):
+                    m[k] = uu * m[k - 1] + (k - 1) * T * m[k - 2]
+                return m
+
+            def g(nodes, J):
+                return [w[i] * mp.fsum(mp.fsum(C[l][k] * nodes[i] ** k for k in range(l + 1)) * J[l] / gam[l]
+                                       for l in range(N + 1)) for i in range(len(nodes))]
+
+            def coeffs(uu):
+                M = moments(uu)
+                return [mp.fsum(C[l][k] * M[k] for k in range(l + 1)) for l in range(N + 1)]
+
+            if self.kind == 'full':
+                return np.array([float(v) for v in g(x, coeffs(u))])
+            gp = g(x, coeffs(u))
+            gm = g(x, coeffs(-u))[::-1]
+            return np.array([float(v) for v in gm + gp])
 
 
 class VelocitySet:

@@ -1,13 +1,18 @@
 """Helpers of the GPU parity tests: run the same seeded instance through the HIP library and
 through the oracle, and compare the populations.
 
-Tolerance (derived): with rounding only, the two FP64 paths agree to
-a few ulp per operation, accumulated over the stages.  Two scales are checked:
+Tolerance (derived): both paths are FP64 and differ by rounding only (summation order,
+fused multiply-adds).  Two scales are checked:
   * normwise: max |F_gpu - F_oracle| / max |F_oracle| <= 1e-12;
-  * per velocity column: max_s |F_gpu - F_oracle| / max_s |F_oracle| <= max(1e-10, 8 eps kappa_v),
-    where kappa_v (``kappa`` below) is the first-order rounding amplification of the
-    Hermite-projected equilibrium (Sec. III) at that velocity; it exceeds 1e5 only at the
-    outermost half-range nodes, whose populations are ~w ~ 1e-15 .. 1e-52.
+  * per velocity column v: max_s |F_gpu - F_oracle| / max_s |F_oracle| <= 1e-10 on every
+    column, the outermost half-range velocities (populations down to 1e-52 of the peak)
+    included.
+The per-column bound holds because both sides evaluate the half-range projection
+coefficients of the equilibrium (Sec. III) with compensated dot products: the coefficients
+cancel (at rest they vanish beyond order 0 while their terms reach 1e3) and the outer nodes
+amplify what is left by up to 1e7, so with plain sums the two evaluations differed there by
+up to 1e-7 relative, while with compensated sums the rest states agree to 1e-15 and the
+columns after 10 steps to 3e-13 (measured on the 800- and 3600-velocity sets).
 """
 import numpy as np
 
@@ -30,25 +35,6 @@ def make_wl(Qx, Qy, Qz, S, scheme, **params):
     base = dict(kn=0.2, u_w=0.3, T_w=1.0, n0=1.0, pr=2.0 / 3.0, law='power', omega=0.7, A=0.0, dt=2e-4)
     base.update(params)
     return dict(Qx=Qx, Qy=Qy, Qz=Qz, S=S, scheme=scheme, params=base)
-
-
-def kappa(model):
-    """Per-velocity first-order rounding amplification of the projected equilibrium: a
-    coefficient J_l = sum_k C_lk M_k (M_k the Gaussian moments) carries an error of a few ulp
-    of sum_k |C_lk| |M_k|, and node i multiplies it by |w_i P_l(x_i) / gamma_l| / w_i
-    relative to its weight; the three axes multiply (oracle tables, u = 0, T = 1 moments)."""
-    from oracle import equilibrium as eq
-    vs = model.vs
-
-    def axis(ax, mom):
-        cl = np.abs(ax.C) @ np.abs(mom)
-        return (np.abs(ax.Phi) * cl).sum(1)
-
-    kx = axis(vs.X, eq.half_gaussian_moments(vs.X.N, 0.0, 1.0)) / vs.X.weights[vs.X.Q:]
-    kx = np.concatenate([kx[::-1], kx])
-    ky = axis(vs.Y, eq.gaussian_moments(vs.Y.N, 0.0, 1.0)) / vs.Y.weights
-    kz = axis(vs.Z, eq.gaussian_moments(vs.Z.N, 0.0, 1.0)) / vs.Z.weights
-    return (kx[:, None, None] * ky[None, :, None] * kz[None, None, :]).ravel()
 
 
 def gpu_run(wl, steps, seeds=None, eps=0.05, params_list=None, launch=None, device='cuda'):
@@ -89,10 +75,8 @@ def compare(Fg, Fo, model):
     err = np.abs(Fg - Fo)
     norm = err.max() / np.abs(Fo).max()
     col = err.max(axis=0) / np.abs(Fo).max(axis=0)
-    tol = np.maximum(COL_TOL, 8 * np.finfo(float).eps * kappa(model))
-    worst = int(np.argmax(col / tol))
-    return dict(norm=norm, col=col.max(), col_over_tol=float((col / tol).max()), worst_v=worst,
-                worst_kappa=float(kappa(model)[worst]))
+    worst = int(np.argmax(col))
+    return dict(norm=norm, col=col.max(), col_over_tol=float(col.max() / COL_TOL), worst_v=worst)
 
 
 def assert_parity(Fg, Fo, model, label=''):
