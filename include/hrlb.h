@@ -40,7 +40,8 @@ extern "C" {
 #define HRLB_EINVAL (-1)   /* invalid argument (sizes, parameters, null pointers)        */
 #define HRLB_ENOMEM (-2)   /* caller buffer smaller than hrlb_state_bytes requires        */
 #define HRLB_EHIP (-3)     /* a HIP runtime call failed; message holds hipGetErrorString  */
-#define HRLB_ENUMERIC (-4) /* n <= 0, T <= 0 or a non-finite moment met during a step     */
+#define HRLB_ENUMERIC (-4) /* n <= 0, T <= 0 or a non-finite moment met during a step, or a
+                              time step beyond the RK3 stability limit (hrlb_init_state)    */
 
 #define HRLB_LAW_POWER 0      /* mu = kn T^omega  -> tau = kn T^(omega-1) / n  (Eq. mw_tau for omega = 1) */
 #define HRLB_LAW_SUTHERLAND 1 /* mu = kn sqrt(T)(1+S)/(1+S/T) -> Eq. sutherland_tau with kn = 1/(delta sqrt 2) */
@@ -81,9 +82,22 @@ const char* hrlb_last_error(void);
  *   Errors: HRLB_EINVAL on out-of-range orders or out == NULL.
  */
 int hrlb_init_quadrature(int Qx, int Nx, int Qy, int Ny, int Qz, int Nz, hrlb_quad** out);
+/*
+ * init_quadrature_reduced -- the paper's own velocity set HHLB(Nx;Qx) x HLB(Ny;Qy) with p_z
+ * integrated out (Sec. III: the reduced distributions phi = int f dp_z and chi = int f p_z^2
+ * dp_z of Eq. reduced_def, evolved by Eq. boltz_red with phi^eq of Eq. phieq, chi^eq =
+ * T phi^eq and the reduced Shakhov factors of Eq. sred_def; at the wall chi_w = T_w phi_w,
+ * App. A.4).  A sim built on it carries V = 4 Qx Qy populations per node, flat index
+ * v = (i Qy + j) 2 + c with c = 0 for phi and c = 1 for chi; everything else (step,
+ * moments with u_z = q_z = P_xz = P_yz = 0 and P_zz = sum chi, residual, batches, launch
+ * shapes) is as for the explicit set.  hrlb_quad_nodes has no axis 2 for it, and
+ * hrlb_seed_state rejects its sims.  Orders as for hrlb_init_quadrature; HRLB_EINVAL
+ * otherwise.
+ */
+int hrlb_init_quadrature_reduced(int Qx, int Nx, int Qy, int Ny, hrlb_quad** out);
 void hrlb_quad_free(hrlb_quad* q);
 
-/* Number of discrete velocities V = 2 Qx Qy Qz. */
+/* Number of populations per node: V = 2 Qx Qy Qz (4 Qx Qy for the reduced model). */
 int hrlb_quad_size(const hrlb_quad* q, int* V);
 
 /*
@@ -116,7 +130,12 @@ int hrlb_state_bytes(const hrlb_quad* q, int S, int batch, size_t* state_bytes, 
  * The quadrature handle must outlive the sim.
  * Errors: HRLB_EINVAL (S < 3, batch < 1, dt <= 0, kn <= 0, T_w <= 0, n0 <= 0, pr <= 0,
  *   A outside [0, 1), unknown law or scheme, one instance's S * V * 8 bytes not below
- *   4 GiB), HRLB_ENOMEM (buffers too small), HRLB_EHIP.
+ *   4 GiB), HRLB_ENUMERIC (a time step beyond the stability limit of the explicit TVD RK3
+ *   scheme, Eq. rk3: Courant number max|p_x| dt / min dx above 0.628 for second-order upwind
+ *   or 1.434 for WENO-5 and its linear form, or dt / tau above 2.512 at the initial state
+ *   (n0, T_w); the limits come from the scheme's amplification factor 1 + z + z^2/2 + z^3/6
+ *   over the Fourier symbols of the linear advection operators and the negative real
+ *   axis), HRLB_ENOMEM (buffers too small), HRLB_EHIP.
  */
 int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* params, int batch,
                     void* d_state, size_t state_bytes, void* d_work, size_t work_bytes, void* stream,
@@ -173,6 +192,18 @@ int hrlb_set_state(hrlb_sim* sim, const double* d_in);
 int hrlb_seed_state(hrlb_sim* sim, const double* d_table, int preserve_mass, int* h_fallback);
 
 /*
+ * free_molecular_state -- overwrite the state with the free-molecular steady state of the
+ * diffuse walls, the collisionless limit of Sec. IV (its shear stress is T_xy^bal of
+ * Eq. Txy_bal): at every node, the populations with p_x < 0 are n0 times the discrete wall
+ * Maxwellian (u_w, T_w) and those with p_x > 0 are their bounce-back images (Eq. widetildei),
+ * i.e. the Maxwellian of the wall at -L/2.  It is a fixed point of the collisionless step, and
+ * the start from which runs at large Kn settle fastest.  Recomputes the moment partials and
+ * clears the numeric-fault flags and residuals; enqueued on the sim's stream.
+ * Errors: HRLB_EINVAL (NULL sim), HRLB_EHIP.
+ */
+int hrlb_free_molecular_state(hrlb_sim* sim);
+
+/*
  * Launch shape of the stage kernel: `cells` nodes marched per thread (1..4096; 0 = the
  * library's default) and `waves` 64-lane waves per workgroup along v (1..4; 0 = default).
  * Any shape gives the same result up to the summation order of the moment partials.
@@ -208,6 +239,9 @@ int hrlb_set_graph(hrlb_sim* sim, int on);
  */
 int hrlb_set_timing(hrlb_sim* sim, int on);
 int hrlb_get_timing(hrlb_sim* sim, double* ms, long long* launches);
+/* The same accumulators per RK3 stage (Eq. rk3): ms[4] and launches[4] receive the stage
+ * kernel's time and launch count of stages 1, 2 and 3, then the closure kernel's. */
+int hrlb_get_stage_timing(hrlb_sim* sim, double* ms, long long* launches);
 
 /*
  * Batches: advance several sims -- each a group of instances sharing one velocity set,

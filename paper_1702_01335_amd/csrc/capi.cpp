@@ -64,8 +64,8 @@ struct hrlb_sim {
   int g_cells, g_waves;   // launch shape the graph was captured with
   std::vector<hipEvent_t> ev;  // pairs (start, stop), kind in ev_kind
   std::vector<int> ev_kind;
-  double ms[2];
-  long long launches[2];
+  double ms[4];          // device time of stage 1, 2, 3 launches and of closure launches
+  long long launches[4];
 };
 
 struct hrlb_batch {
@@ -138,6 +138,8 @@ static Shape make_shape(const QuadTables& t, int S, int B, int scheme) {
   sh.S = S;
   sh.B = B;
   sh.scheme = scheme;
+  sh.reduced = t.reduced;
+  sh.pad = 0;
   // whole 128-byte lines per node record
   int rl = REC_HEAD + 2 * t.Qx + sh.QyQz;
   sh.rec_len = (rl + 15) & ~15;
@@ -199,6 +201,28 @@ int hrlb_init_quadrature(int Qx, int Nx, int Qy, int Ny, int Qz, int Nz, hrlb_qu
   return HRLB_OK;
 }
 
+int hrlb_init_quadrature_reduced(int Qx, int Nx, int Qy, int Ny, hrlb_quad** out) {
+  if (!out) return fail(HRLB_EINVAL, "init_quadrature_reduced: out is NULL");
+  *out = nullptr;
+  if (Qx < 1 || Qx > QX_MAX) return fail(HRLB_EINVAL, "init_quadrature_reduced: Qx must be in 1..128");
+  if (Nx < 0 || Nx > std::min(Qx - 1, NX_MAX))
+    return fail(HRLB_EINVAL, "init_quadrature_reduced: need 0 <= Nx <= min(Qx-1, 8)");
+  if (Qy < 1 || Qy > QYZ_MAX) return fail(HRLB_EINVAL, "init_quadrature_reduced: Qy must be in 1..16");
+  if (Ny < 0 || Ny > Qy - 1) return fail(HRLB_EINVAL, "init_quadrature_reduced: need 0 <= Ny <= Qy-1");
+  hrlb_quad* q = new hrlb_quad;
+  build_quadrature(Qx, Nx, Qy, Ny, 1, 0, q->t);
+  // the z axis becomes the pair of reduced distributions (phi, chi): no p_z, and a z factor
+  // of the equilibrium of 1 for phi and T for chi, which the kernels form themselves
+  q->t.Qz = 2;
+  q->t.Nz = 0;
+  q->t.pz.assign(2, 0.0);
+  q->t.wz.assign(2, 1.0);
+  q->t.phiz.assign(2, 1.0);
+  q->t.reduced = 1;
+  *out = q;
+  return HRLB_OK;
+}
+
 void hrlb_quad_free(hrlb_quad* q) { delete q; }
 
 int hrlb_quad_size(const hrlb_quad* q, int* V) {
@@ -217,6 +241,7 @@ int hrlb_quad_nodes(const hrlb_quad* q, int axis, double* nodes, double* weights
     p = &q->t.py;
     w = &q->t.wy;
   } else if (axis == 2) {
+    if (q->t.reduced) return fail(HRLB_EINVAL, "quad_nodes: the reduced (phi, chi) model has no p_z axis");
     p = &q->t.pz;
     w = &q->t.wz;
   } else {
@@ -257,6 +282,43 @@ static int check_instances(const char* fn, int S, int scheme, const hrlb_params*
       return fail(HRLB_EINVAL, f + ": unknown law" + at);
     if (p.law == HRLB_LAW_SUTHERLAND && !(p.suth_S >= 0)) return fail(HRLB_EINVAL, f + ": suth_S must be >= 0" + at);
     if (!std::isfinite(p.u_w) || !std::isfinite(p.omega)) return fail(HRLB_EINVAL, f + ": non-finite u_w/omega" + at);
+  }
+  return HRLB_OK;
+}
+
+// RK3 (Eq. rk3) stability limits of the linearised schemes, from the amplification factor
+// 1 + z + z^2/2 + z^3/6 over the Fourier symbols of the advection operators: Courant number
+// max|p_x| dt / dx up to 0.628 for second-order upwind and 1.434 for the fifth-order
+// candidates with the ideal weights (the linear part of WENO-5); dt / tau up to 2.512 on
+// the negative real axis for the relaxation.
+constexpr double CFL_UPWIND2 = 0.628, CFL_WENO5 = 1.434, RELAX_RK3 = 2.512;
+
+// A time step beyond these limits cannot give a bounded solution: reject it before any
+// device use.  The relaxation limit is checked at the initial state (n0, T_w); a state that
+// later grows stiffer shows up as a numerical fault in the step.
+static int check_stability(const char* fn, const QuadTables& t, int S, int scheme, const hrlb_params* params,
+                           int batch) {
+  double pmax = 0.0;
+  for (double p : t.px) pmax = std::max(pmax, std::fabs(p));
+  const double lim = scheme == HRLB_SCHEME_UPWIND2 ? CFL_UPWIND2 : CFL_WENO5;
+  for (int b = 0; b < batch; ++b) {
+    const hrlb_params& p = params[b];
+    double dxmin = 1e300;
+    for (int c = 0; c < S; ++c) dxmin = std::min(dxmin, node_x(c + 1.5, S, p.A) - node_x(c + 0.5, S, p.A));
+    const double courant = pmax * p.dt / dxmin;
+    const std::string at = " (instance " + std::to_string(b) + ")";
+    if (courant > lim)
+      return fail(HRLB_ENUMERIC, std::string(fn) + ": time step beyond the RK3 stability limit of the advection: Courant number " +
+                                     std::to_string(courant) + " > " + std::to_string(lim) + at);
+    if (!p.collisionless) {
+      const double T = p.T_w, n = p.n0;
+      const double tau = p.law == HRLB_LAW_POWER        ? p.kn * std::pow(T, p.omega - 1.0) / n
+                         : p.law == HRLB_LAW_SUTHERLAND ? p.kn * (1.0 + p.suth_S) / (n * std::sqrt(T) * (1.0 + p.suth_S / T))
+                                                        : p.kn / std::sqrt(2.0);
+      if (p.dt / tau > RELAX_RK3)
+        return fail(HRLB_ENUMERIC, std::string(fn) + ": time step beyond the RK3 stability limit of the relaxation: dt / tau = " +
+                                       std::to_string(p.dt / tau) + " > " + std::to_string(RELAX_RK3) + at);
+    }
   }
   return HRLB_OK;
 }
@@ -355,6 +417,7 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
     return fail(HRLB_EINVAL, "init_state: buffers must be 256-byte aligned");
   const Shape sh = make_shape(q->t, S, batch, scheme);
   if (!instance_fits(sh)) return fail(HRLB_EINVAL, "init_state: one instance's populations (S * V * 8 bytes) must stay below 4 GiB");
+  if ((rc = check_stability("init_state", q->t, S, scheme, params, batch)) != HRLB_OK) return rc;
   const WorkLayout L = work_layout(sh);
   const size_t arr = align256((size_t)batch * S * sh.V * sizeof(double));
   if (state_bytes < 3 * arr) return fail(HRLB_ENOMEM, "init_state: state buffer smaller than hrlb_state_bytes");
@@ -373,8 +436,10 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
   s->gexec = nullptr;
   s->cap_stream = nullptr;
   s->g_cells = s->g_waves = 0;
-  s->ms[0] = s->ms[1] = 0;
-  s->launches[0] = s->launches[1] = 0;
+  for (int k = 0; k < 4; ++k) {
+    s->ms[k] = 0;
+    s->launches[k] = 0;
+  }
   s->d = carve(L, (char*)d_work, (char*)d_state, arr);
   const DevPtrs& d = s->d;
   hipStream_t st = s->stream;
@@ -403,6 +468,7 @@ int hrlb_step_noalloc(const hrlb_quad* q, int S, int scheme, const hrlb_params* 
   const Shape sh = make_shape(q->t, S, batch, scheme);
   if (!instance_fits(sh))
     return fail(HRLB_EINVAL, "step_noalloc: one instance's populations (S * V * 8 bytes) must stay below 4 GiB");
+  if ((rc = check_stability("step_noalloc", q->t, S, scheme, params, batch)) != HRLB_OK) return rc;
   const WorkLayout L = work_layout(sh);
   if (L.total > SCRATCH_BYTES)
     return fail(HRLB_ENOMEM, "step_noalloc: this batch needs " + std::to_string(L.total) +
@@ -540,11 +606,11 @@ int hrlb_step(hrlb_sim* s, int nsteps) {
       hipEvent_t e0 = nullptr;
       hipError_t e = ev_begin(s, &e0);
       if (e == hipSuccess) e = (hipError_t)launch_closure(sh, d, Fin, s->part_nvb, nullptr, s->stream);
-      if (e == hipSuccess) e = ev_end(s, e0, 1);
+      if (e == hipSuccess) e = ev_end(s, e0, 3);
       if (e == hipSuccess) e = ev_begin(s, &e0);
       if (e == hipSuccess)
         e = (hipError_t)launch_stage(sh, d, stage, Fin, d.F[0], Fout, s->cells, s->waves, s->stream);
-      if (e == hipSuccess) e = ev_end(s, e0, 0);
+      if (e == hipSuccess) e = ev_end(s, e0, stage - 1);
       if (e != hipSuccess) return hip_fail(e, "step: launch");
       s->part_nvb = nvb;
     }
@@ -1016,8 +1082,20 @@ int hrlb_set_state(hrlb_sim* s, const double* d_in) {
   return HRLB_OK;
 }
 
+int hrlb_free_molecular_state(hrlb_sim* s) {
+  if (!s) return fail(HRLB_EINVAL, "free_molecular_state: sim is NULL");
+  hipError_t e = (hipError_t)launch_fm_state(s->sh, s->d, s->stream);
+  if (e == hipSuccess) e = (hipError_t)launch_clear_flags(s->sh, s->d, s->stream);
+  if (e == hipSuccess) e = (hipError_t)launch_partials(s->sh, s->d, s->d.F[0], s->cells, s->waves, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "free_molecular_state: launch");
+  s->part_nvb = (s->sh.V + 64 * s->waves - 1) / (64 * s->waves);
+  s->resid_nres = 0;
+  return HRLB_OK;
+}
+
 int hrlb_seed_state(hrlb_sim* s, const double* d_table, int preserve_mass, int* h_fallback) {
   if (!s || !d_table) return fail(HRLB_EINVAL, "seed_state: NULL argument");
+  if (s->sh.reduced) return fail(HRLB_EINVAL, "seed_state: not available for the reduced (phi, chi) model");
   hipError_t e = (hipError_t)launch_seed(s->sh, s->d, d_table, preserve_mass ? 1 : 0, s->stream);
   if (e != hipSuccess) return hip_fail(e, "seed_state: launch");
   if (h_fallback)
@@ -1057,14 +1135,15 @@ int hrlb_set_timing(hrlb_sim* s, int on) {
   for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
   s->ev.clear();
   s->ev_kind.clear();
-  s->ms[0] = s->ms[1] = 0;
-  s->launches[0] = s->launches[1] = 0;
+  for (int k = 0; k < 4; ++k) {
+    s->ms[k] = 0;
+    s->launches[k] = 0;
+  }
   s->timing = on != 0;
   return HRLB_OK;
 }
 
-int hrlb_get_timing(hrlb_sim* s, double* ms, long long* launches) {
-  if (!s || !ms || !launches) return fail(HRLB_EINVAL, "get_timing: NULL argument");
+static int collect_timing(hrlb_sim* s) {
   HIP_TRY(hipStreamSynchronize(s->stream), "get_timing: synchronize");
   for (size_t k = 0; k < s->ev_kind.size(); ++k) {
     float t = 0;
@@ -1076,10 +1155,28 @@ int hrlb_get_timing(hrlb_sim* s, double* ms, long long* launches) {
   }
   s->ev.clear();
   s->ev_kind.clear();
-  ms[0] = s->ms[0];
-  ms[1] = s->ms[1];
-  launches[0] = s->launches[0];
-  launches[1] = s->launches[1];
+  return HRLB_OK;
+}
+
+int hrlb_get_timing(hrlb_sim* s, double* ms, long long* launches) {
+  if (!s || !ms || !launches) return fail(HRLB_EINVAL, "get_timing: NULL argument");
+  int rc = collect_timing(s);
+  if (rc != HRLB_OK) return rc;
+  ms[0] = s->ms[0] + s->ms[1] + s->ms[2];
+  ms[1] = s->ms[3];
+  launches[0] = s->launches[0] + s->launches[1] + s->launches[2];
+  launches[1] = s->launches[3];
+  return HRLB_OK;
+}
+
+int hrlb_get_stage_timing(hrlb_sim* s, double* ms, long long* launches) {
+  if (!s || !ms || !launches) return fail(HRLB_EINVAL, "get_stage_timing: NULL argument");
+  int rc = collect_timing(s);
+  if (rc != HRLB_OK) return rc;
+  for (int k = 0; k < 4; ++k) {
+    ms[k] = s->ms[k];
+    launches[k] = s->launches[k];
+  }
   return HRLB_OK;
 }
 

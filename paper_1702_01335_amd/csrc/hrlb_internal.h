@@ -20,9 +20,12 @@ constexpr int MAX_WAVES = 4;   // waves per stage-kernel workgroup (LDS: 8.3 KB 
 // a workgroup of up to MAX_WAVES waves can hold past V
 constexpr int ptab_blocks(int V) { return (V + 63) / 64 + MAX_WAVES - 1; }
 
-// Host quadrature tables (double, rounded from long double).
+// Host quadrature tables (double, rounded from long double).  In the reduced (phi, chi)
+// model the z axis is replaced by the two reduced distributions: Qz = 2 "components"
+// (0: phi, 1: chi), pz = {0, 0}, and the z factor of the equilibrium is {1, T}.
 struct QuadTables {
   int Qx, Nx, Qy, Ny, Qz, Nz;
+  int reduced;
   std::vector<double> px, wx;    // 2 Qx, ascending
   std::vector<double> py, wy;    // Qy
   std::vector<double> pz, wz;    // Qz
@@ -78,6 +81,8 @@ struct Shape {
   int V, QyQz, S, B;
   int scheme;
   int rec_len;        // REC_HEAD + 2 Qx + Qy Qz, rounded up to a multiple of 16 (whole lines)
+  int reduced;        // 1: the paper's reduced (phi, chi) model, Qz = 2 components
+  int pad;
 };
 
 // One uniform group (one sim) inside a batch, as the batched kernels see it.
@@ -103,6 +108,7 @@ int set_error(int code, const char* msg);
 
 int launch_setup_tables(const Shape& sh, const DevPtrs& d, void* stream);
 int launch_init_state(const Shape& sh, const DevPtrs& d, const double* perturb, double eps, void* stream);
+int launch_fm_state(const Shape& sh, const DevPtrs& d, void* stream);
 int launch_seed(const Shape& sh, const DevPtrs& d, const double* tab, int preserve_mass, void* stream);
 int launch_clear_flags(const Shape& sh, const DevPtrs& d, void* stream);
 int launch_partials(const Shape& sh, const DevPtrs& d, const double* F, int cells, int waves, void* stream);

@@ -110,23 +110,45 @@ __device__ __forceinline__ double interp(double a, double b, double c, double d,
 
 // Half-range Gaussian moments I_k(u, T) = int_0^inf p^k G(p; u, T) dp, k <= NX_MAX:
 // I_0 = erfc(-u / sqrt(2T)) / 2, I_1 = u I_0 + T G(0), I_k = u I_{k-1} + (k-1) T I_{k-2}.
+// The square root and divisions are the correctly rounded ones, so that at rest (u = 0) the
+// moments are the same doubles on any IEEE machine.
 __device__ __forceinline__ void half_gauss_moments(double u, double T, double* I) {
-  const double G0 = exp(-u * u / (2.0 * T)) * rsqrt(2.0 * M_PI * T);
-  I[0] = 0.5 * erfc(-u * rsqrt(2.0 * T));
+  const double G0 = exp(-u * u / (2.0 * T)) / sqrt(2.0 * M_PI * T);
+  I[0] = 0.5 * erfc(-u / sqrt(2.0 * T));
   I[1] = u * I[0] + T * G0;
 #pragma unroll
   for (int k = 2; k <= NX_MAX; ++k) I[k] = u * I[k - 1] + (k - 1) * T * I[k - 2];
 }
 
-// Coefficients J_l = int G h_l over one semi-axis (monic half-range h_l, l <= Nx).
+// Coefficients J_l = int G h_l over one semi-axis (monic half-range h_l, l <= Nx), as the
+// dot product sum_k C_lk I_k of the monomial coefficients with the half-range moments.  The
+// terms cancel (at rest J_l vanishes for l >= 1 while the terms reach 1e3), and the outer
+// half-range nodes multiply what is left of J_l by up to 1e7 (Qx = 50), so the product is
+// summed by the compensated algorithm Dot2 of Ogita, Rump and Oishi (2005): exact products
+// (fma), exact two-term sums, the rounding errors summed on the side; the result is as
+// accurate as a dot product in twice the precision.  The compiler must not contract the
+// two-term sums into fused multiply-adds, which would break their exactness.
 __device__ __forceinline__ void half_projection(const double* __restrict__ cx, int Nx, const double* I, double* J) {
+#pragma clang fp contract(off)
 #pragma unroll
   for (int l = 0; l <= NX_MAX; ++l) {
-    double s = 0.0;
+    double p = 0.0, s = 0.0;
+    if (l <= Nx) {
+      const double* c = cx + l * (Nx + 1);
+      p = c[0] * I[0];
+      s = fma(c[0], I[0], -p);
 #pragma unroll
-    for (int k = 0; k <= NX_MAX; ++k)
-      if (k <= l && l <= Nx) s += cx[l * (Nx + 1) + k] * I[k];
-    J[l] = s;
+      for (int k = 1; k <= l; ++k) {
+        const double h = c[k] * I[k];
+        const double r = fma(c[k], I[k], -h);
+        const double t = p + h;
+        const double bb = t - p;
+        const double q = (p - (t - bb)) + (h - bb);
+        p = t;
+        s = s + (q + r);
+      }
+    }
+    J[l] = p + s;
   }
 }
 
@@ -181,7 +203,9 @@ __global__ void __launch_bounds__(256) setup_tables_kernel(Shape sh, DevPtrs d) 
     gy0[j] = full_node(d.phiy, sh.Ny, j, a0);
     gyw[j] = full_node(d.phiy, sh.Ny, j, aw);
   }
-  for (int k = threadIdx.x; k < sh.Qz; k += blockDim.x) gz0[k] = full_node(d.phiz, sh.Nz, k, a0);
+  // reduced (phi, chi) model: the z factor is 1 for phi and T for chi (chi^eq = T phi^eq)
+  for (int k = threadIdx.x; k < sh.Qz; k += blockDim.x)
+    gz0[k] = sh.reduced ? (k == 0 ? 1.0 : in.T_w) : full_node(d.phiz, sh.Nz, k, a0);
   if (b == 0) {
     // moment multipliers of each velocity (1, p, p_a p_b, p^2 p), the A operand of the
     // moment contraction, in operand order: for the wave of velocities 64 w .. 64 w + 63,
@@ -198,7 +222,10 @@ __global__ void __launch_bounds__(256) setup_tables_kernel(Shape sh, DevPtrs d) 
         const double px = d.px[i], py = d.py[j], pz = d.pz[k], p2 = px * px + py * py + pz * pz;
         const double m[NMOM] = {1.0, px, py, pz, px * px, py * py, pz * pz, px * py, px * pz, py * pz,
                                 p2 * px, p2 * py, p2 * pz};
-        val = m[q];
+        // in the reduced model (p_z = 0) phi takes the multipliers above, and chi = int f p_z^2
+        // dp_z carries p_z^2 (for P_zz) and p_z^2 p_a (for q_a), Eq. qdef with p_z integrated out
+        const double mchi[NMOM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, px, py, 0.0};
+        val = (sh.reduced && k == 1) ? mchi[q] : m[q];
       }
       d.ptab[idx] = val;
     }
@@ -211,7 +238,7 @@ __global__ void __launch_bounds__(256) setup_tables_kernel(Shape sh, DevPtrs d) 
     const double gw = gx0[i] * gyw[j] * gz0[k];
     d.g_rest[(size_t)b * sh.V + v] = gr;
     d.g_wall[(size_t)b * sh.V + v] = gw;
-    if (i < sh.Qx) acc += d.px[i] * gw;
+    if (i < sh.Qx && !(sh.reduced && k == 1)) acc += d.px[i] * gw;  // mass flux: phi only
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -231,6 +258,21 @@ __global__ void init_state_kernel(Shape sh, DevPtrs d, const double* __restrict_
     double f = d.inst[b].n0 * d.g_rest[(size_t)b * sh.V + v];
     if (r) f *= 1.0 + eps * r[idx];
     d.F[0][idx] = f;
+  }
+}
+
+// the free-molecular steady state of diffuse walls (the collisionless limit of Sec. IV, whose
+// shear stress is Eq. Txy_bal): the populations leaving the wall at x = L/2 (p_x < 0) are
+// n0 times its Maxwellian, those with p_x > 0 the bounce-back images of these (the
+// Maxwellian of the wall at -L/2), the same at every node
+__global__ void fm_state_kernel(Shape sh, DevPtrs d) {
+  const size_t total = (size_t)sh.B * sh.S * sh.V;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / ((size_t)sh.S * sh.V));
+    const int v = (int)(idx % sh.V);
+    const int i = v / sh.QyQz, jk = v - i * sh.QyQz, j = jk / sh.Qz, k = jk - j * sh.Qz;
+    const int vm = ((2 * sh.Qx - 1 - i) * sh.Qy + (sh.Qy - 1 - j)) * sh.Qz + k;
+    d.F[0][idx] = d.inst[b].n0 * d.g_wall[(size_t)b * sh.V + (i < sh.Qx ? v : vm)];
   }
 }
 
@@ -488,7 +530,8 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int v = min(v0 + 64 * k, V - 1);
-        px[k] = (v0 + 64 * k < V) ? gmem(d.px)[v / sh.QyQz] : 0.0;
+        // mass flux: every population, or phi alone in the reduced model (odd v are chi)
+        px[k] = (v0 + 64 * k < V && !(sh.reduced && (v & 1))) ? gmem(d.px)[v / sh.QyQz] : 0.0;
         f3[k] = F[(size_t)(S - 3) * V + v];
         f2[k] = F[(size_t)(S - 2) * V + v];
         f1[k] = F[(size_t)(S - 1) * V + v];
@@ -686,7 +729,9 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
   for (int idx = lane; idx < nblk_nodes * Qyz; idx += 64) {
     const int nd = idx / Qyz, e = idx - nd * Qyz;
     const double* sn = scal + nd * SC;
-    gyz[nd * Qyz + e] = (e < sh.Qy) ? full_node(phiy, sh.Ny, e, sn + oay) : full_node(phiz, sh.Nz, e - sh.Qy, sn + oaz);
+    gyz[nd * Qyz + e] = (e < sh.Qy)   ? full_node(phiy, sh.Ny, e, sn + oay)
+                        : sh.reduced ? (e == sh.Qy ? 1.0 : msum[nd * PART_STRIDE + NMOM + 2])  // 1 for phi, T for chi
+                                     : full_node(phiz, sh.Nz, e - sh.Qy, sn + oaz);
   }
   __syncthreads();
   // 4) the coalesced fill of the equilibrium tables, n g_x on the 2Qx nodes, then g_y g_z on
@@ -808,7 +853,9 @@ __device__ __forceinline__ double stencil_flux(bool pos, double px, double w0, d
 // depth of the stage kernel's load pipeline (nodes ahead); divides 16
 constexpr int PIPE = 4;
 
-template <int SCHEME, int STAGE>
+// RED: the reduced (phi, chi) model of Sec. III (Eqs. reduced_def, boltz_red, sred_def), the
+// z index being the component (0: phi, 1: chi) and p_z absent
+template <int SCHEME, int STAGE, bool RED>
 __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, const double* __restrict__ Fin,
                                            const double* Fl, double* Fout, int b, int vb, int ch, int nvb, int nch,
                                            int cs, double* lds) {
@@ -822,6 +869,11 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   const int vv = active ? v : V - 1;
   const int i = vv / sh.QyQz, jk = vv - i * sh.QyQz, j = jk / sh.Qz, k = jk - j * sh.Qz;
   const double px = gmem(d.px)[i], py = gmem(d.py)[j], pz = gmem(d.pz)[k];
+  // reduced Shakhov factors (Eq. sred_def): integrating (xi^2 / 5T - 1) over p_z against the
+  // Maxwellian leaves xi_perp^2 / 5T - 4/5 for phi and xi_perp^2 / 5T - 2/5 for chi (the
+  // p_z^2 and p_z^4 moments T and 3 T^2), so the constant term of Eq. sdef is scaled by
+  // 4/5 or 2/5
+  const double cmul = RED ? (k == 0 ? 0.8 : 0.4) : 1.0;
   const bool pos = px > 0.0;
   const int vm = ((2 * Qx - 1 - i) * sh.Qy + (sh.Qy - 1 - j)) * sh.Qz + k;  // bounce-back partner
   const size_t base = (size_t)b * S * V;
@@ -909,10 +961,19 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
     const double feq = p.gx * p.gyz;
     double FS = feq;
     if (z.cs != 0.0) {
-      const double xx = px - z.ux, xy = py - z.uy, xz = pz - z.uz;
-      const double xi2 = xx * xx + xy * xy + xz * xz;
-      const double qxi = z.qx * xx + z.qy * xy + z.qz * xz;
-      FS = feq + feq * ((z.a * xi2 - z.cs) * qxi);  // F^eq (1 + S), Eq. sdef
+      if constexpr (RED) {
+        (void)pz;
+        const double xx = px - z.ux, xy = py - z.uy;
+        const double xi2 = xx * xx + xy * xy;
+        const double qxi = z.qx * xx + z.qy * xy;
+        FS = feq + feq * ((z.a * xi2 - z.cs * cmul) * qxi);  // phi^eq (1 + S_phi), T phi^eq (1 + S_chi)
+      } else {
+        (void)cmul;
+        const double xx = px - z.ux, xy = py - z.uy, xz = pz - z.uz;
+        const double xi2 = xx * xx + xy * xy + xz * xz;
+        const double qxi = z.qx * xx + z.qy * xy + z.qz * xz;
+        FS = feq + feq * ((z.a * xi2 - z.cs) * qxi);  // F^eq (1 + S), Eq. sdef
+      }
     }
     const double G = F + (FS - F) * z.itau - D;  // F + dt L[F], Eq. L_def
     double out;
@@ -1011,14 +1072,14 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
 }
 
 // the stage kernels are held to three waves per SIMD (at most 168 VGPRs)
-template <int SCHEME, int STAGE>
+template <int SCHEME, int STAGE, bool RED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) stage_kernel(Shape sh, DevPtrs d, const double* __restrict__ Fin,
                                                     const double* Fl, double* Fout, int nvb, int nch, int cs) {
   extern __shared__ double lds[];
   int t = xcd_tile(blockIdx.x, gridDim.x);
   const int ch = t % nch;
   t /= nch;
-  stage_tile<SCHEME, STAGE>(sh, d, Fin, Fl, Fout, t / nvb, t % nvb, ch, nvb, nch, cs, lds);
+  stage_tile<SCHEME, STAGE, RED>(sh, d, Fin, Fl, Fout, t / nvb, t % nvb, ch, nvb, nch, cs, lds);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1035,12 +1096,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) b
   const GroupDesc& g = groups[tl.x];
   const double* Fin = g.d.F[STAGE - 1];
   double* Fout = g.d.F[STAGE % 3];
-  if (g.sh.scheme == 1)
-    stage_tile<1, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
-  else if (g.sh.scheme == 2)
-    stage_tile<2, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
-  else
-    stage_tile<0, STAGE>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
+  if (g.sh.reduced) {
+    if (g.sh.scheme == 1)
+      stage_tile<1, STAGE, true>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
+    else if (g.sh.scheme == 2)
+      stage_tile<2, STAGE, true>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
+    else
+      stage_tile<0, STAGE, true>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
+  } else if (g.sh.scheme == 1) {
+    stage_tile<1, STAGE, false>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
+  } else if (g.sh.scheme == 2) {
+    stage_tile<2, STAGE, false>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
+  } else {
+    stage_tile<0, STAGE, false>(g.sh, g.d, Fin, g.d.F[0], Fout, tl.y, tl.z, tl.w, g.nvb, g.nch, g.cs, lds);
+  }
 }
 
 __global__ void __launch_bounds__(64) batch_closure_kernel(const GroupDesc* __restrict__ groups,
@@ -1097,6 +1166,13 @@ int launch_init_state(const Shape& sh, const DevPtrs& d, const double* perturb, 
   return (int)hipGetLastError();
 }
 
+int launch_fm_state(const Shape& sh, const DevPtrs& d, void* stream) {
+  const size_t total = (size_t)sh.B * sh.S * sh.V;
+  const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(fm_state_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, sh, d);
+  return (int)hipGetLastError();
+}
+
 int launch_seed(const Shape& sh, const DevPtrs& d, const double* tab, int preserve_mass, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(seed_check_kernel, dim3(sh.B), dim3(256), 0, st, sh, d, tab, preserve_mass);
@@ -1129,31 +1205,38 @@ int launch_closure(const Shape& sh, const DevPtrs& d, const double* Fin, int nvb
   return (int)hipGetLastError();
 }
 
-template <int SCHEME, int STAGE>
+template <int SCHEME, int STAGE, bool RED>
 static int launch_stage_t(const Shape& sh, const DevPtrs& d, const double* Fin, const double* Fl, double* Fout,
                           int cells, int waves, void* stream) {
   int nvb, nch;
   const int nblk = grid_tiles(sh, cells, waves, &nvb, &nch);
-  hipLaunchKernelGGL((stage_kernel<SCHEME, STAGE>), dim3(nblk), dim3(64 * waves), stage_lds_bytes(waves),
+  hipLaunchKernelGGL((stage_kernel<SCHEME, STAGE, RED>), dim3(nblk), dim3(64 * waves), stage_lds_bytes(waves),
                      (hipStream_t)stream, sh, d, Fin, Fl, Fout, nvb, nch, cells);
   return (int)hipGetLastError();
 }
 
-int launch_stage(const Shape& sh, const DevPtrs& d, int stage, const double* Fin, const double* Fl, double* Fout,
-                 int cells, int waves, void* stream) {
+template <bool RED>
+static int launch_stage_r(const Shape& sh, const DevPtrs& d, int stage, const double* Fin, const double* Fl,
+                          double* Fout, int cells, int waves, void* stream) {
   if (sh.scheme == 1) {
-    if (stage == 1) return launch_stage_t<1, 1>(sh, d, Fin, Fl, Fout, cells, waves, stream);
-    if (stage == 2) return launch_stage_t<1, 2>(sh, d, Fin, Fl, Fout, cells, waves, stream);
-    return launch_stage_t<1, 3>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+    if (stage == 1) return launch_stage_t<1, 1, RED>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+    if (stage == 2) return launch_stage_t<1, 2, RED>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+    return launch_stage_t<1, 3, RED>(sh, d, Fin, Fl, Fout, cells, waves, stream);
   }
   if (sh.scheme == 2) {
-    if (stage == 1) return launch_stage_t<2, 1>(sh, d, Fin, Fl, Fout, cells, waves, stream);
-    if (stage == 2) return launch_stage_t<2, 2>(sh, d, Fin, Fl, Fout, cells, waves, stream);
-    return launch_stage_t<2, 3>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+    if (stage == 1) return launch_stage_t<2, 1, RED>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+    if (stage == 2) return launch_stage_t<2, 2, RED>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+    return launch_stage_t<2, 3, RED>(sh, d, Fin, Fl, Fout, cells, waves, stream);
   }
-  if (stage == 1) return launch_stage_t<0, 1>(sh, d, Fin, Fl, Fout, cells, waves, stream);
-  if (stage == 2) return launch_stage_t<0, 2>(sh, d, Fin, Fl, Fout, cells, waves, stream);
-  return launch_stage_t<0, 3>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+  if (stage == 1) return launch_stage_t<0, 1, RED>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+  if (stage == 2) return launch_stage_t<0, 2, RED>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+  return launch_stage_t<0, 3, RED>(sh, d, Fin, Fl, Fout, cells, waves, stream);
+}
+
+int launch_stage(const Shape& sh, const DevPtrs& d, int stage, const double* Fin, const double* Fl, double* Fout,
+                 int cells, int waves, void* stream) {
+  if (sh.reduced) return launch_stage_r<true>(sh, d, stage, Fin, Fl, Fout, cells, waves, stream);
+  return launch_stage_r<false>(sh, d, stage, Fin, Fl, Fout, cells, waves, stream);
 }
 
 int launch_residual(const Shape& sh, const DevPtrs& d, int nres, void* stream) {

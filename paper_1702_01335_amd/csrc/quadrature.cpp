@@ -183,6 +183,7 @@ int build_quadrature(int Qx, int Nx, int Qy, int Ny, int Qz, int Nz, QuadTables&
   qt.Ny = Ny;
   qt.Qz = Qz;
   qt.Nz = Nz;
+  qt.reduced = 0;
   // ---- x axis ----
   std::vector<ld> a, b, xh, wh;
   half_range_recurrence(Qx + 1, a, b);

@@ -25,7 +25,8 @@ EXPORTS = ('hrlb_last_error', 'hrlb_init_quadrature', 'hrlb_quad_free', 'hrlb_qu
            'hrlb_get_state', 'hrlb_set_state', 'hrlb_set_launch', 'hrlb_get_launch', 'hrlb_autotune', 'hrlb_set_graph',
            'hrlb_set_timing', 'hrlb_get_timing', 'hrlb_batch_bytes', 'hrlb_batch_create', 'hrlb_batch_step',
            'hrlb_batch_residual', 'hrlb_batch_set_active', 'hrlb_batch_info', 'hrlb_batch_free', 'hrlb_seed_state',
-           'hrlb_step_noalloc')
+           'hrlb_step_noalloc', 'hrlb_free_molecular_state', 'hrlb_get_stage_timing',
+           'hrlb_init_quadrature_reduced')
 SCRATCH_BYTES = 32 << 20  # HRLB_SCRATCH_BYTES
 
 
@@ -67,6 +68,7 @@ def load():
     lib.hrlb_last_error.restype = ctypes.c_char_p
     lib.hrlb_last_error.argtypes = []
     lib.hrlb_init_quadrature.argtypes = [ctypes.c_int] * 6 + [ctypes.POINTER(vp)]
+    lib.hrlb_init_quadrature_reduced.argtypes = [ctypes.c_int] * 4 + [ctypes.POINTER(vp)]
     lib.hrlb_quad_free.argtypes = [vp]
     lib.hrlb_quad_free.restype = None
     lib.hrlb_quad_size.argtypes = [vp, ip]
@@ -82,12 +84,14 @@ def load():
     lib.hrlb_get_state.argtypes = [vp, vp]
     lib.hrlb_set_state.argtypes = [vp, vp]
     lib.hrlb_seed_state.argtypes = [vp, vp, ctypes.c_int, ip]
+    lib.hrlb_free_molecular_state.argtypes = [vp]
     lib.hrlb_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.hrlb_get_launch.argtypes = [vp, ip, ip]
     lib.hrlb_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ip, ip, dp]
     lib.hrlb_set_graph.argtypes = [vp, ctypes.c_int]
     lib.hrlb_set_timing.argtypes = [vp, ctypes.c_int]
     lib.hrlb_get_timing.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
+    lib.hrlb_get_stage_timing.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
     lib.hrlb_batch_bytes.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz)]
     lib.hrlb_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, sz, vp,
                                       ctypes.POINTER(vp)]
@@ -117,6 +121,12 @@ def _check(rc):
 def init_quadrature(Qx, Nx, Qy, Ny, Qz, Nz):
     h = ctypes.c_void_p()
     _check(load().hrlb_init_quadrature(Qx, Nx, Qy, Ny, Qz, Nz, ctypes.byref(h)))
+    return h
+
+
+def init_quadrature_reduced(Qx, Nx, Qy, Ny):
+    h = ctypes.c_void_p()
+    _check(load().hrlb_init_quadrature_reduced(Qx, Nx, Qy, Ny, ctypes.byref(h)))
     return h
 
 
@@ -176,6 +186,8 @@ class Quadrature:
         _check(load().hrlb_quad_size(self.handle, ctypes.byref(v)))
         self.V = v.value
 
+    reduced = False
+
     def nodes(self, axis):
         n = {0: 2 * self.Qx, 1: self.Qy, 2: self.Qz}[axis]
         p, w = np.zeros(n), np.zeros(n)
@@ -187,6 +199,23 @@ class Quadrature:
         if getattr(self, 'handle', None) and _lib is not None:
             _lib.hrlb_quad_free(self.handle)
             self.handle = None
+
+
+class ReducedQuadrature(Quadrature):
+    """The paper's HHLB(Nx;Qx) x HLB(Ny;Qy) with p_z integrated out: populations phi and chi
+    (Eq. reduced_def) per velocity, flat index (i Qy + j) 2 + c, c = 0 phi, 1 chi."""
+
+    reduced = True
+
+    def __init__(self, Qx, Qy, Nx=None, Ny=None):
+        self.Qx, self.Qy, self.Qz = Qx, Qy, 2
+        self.Nx = min(6, Qx - 1) if Nx is None else Nx
+        self.Ny = Qy - 1 if Ny is None else Ny
+        self.Nz = 0
+        self.handle = init_quadrature_reduced(Qx, self.Nx, Qy, self.Ny)
+        v = ctypes.c_int()
+        _check(load().hrlb_quad_size(self.handle, ctypes.byref(v)))
+        self.V = v.value
 
 
 class Solver:
@@ -210,7 +239,8 @@ class Solver:
             perturb = perturb.to(device=self.device, dtype=torch.float64).contiguous()
             assert tuple(perturb.shape) == (self.B, S, self.V)
         self._perturb = perturb
-        self.handle = init_state(quad.handle, S, self.scheme, list(params), self.state, self.work,
+        self.params = list(params)
+        self.handle = init_state(quad.handle, S, self.scheme, self.params, self.state, self.work,
                                  self.stream.cuda_stream, perturb, eps)
 
     def step(self, nsteps=1):
@@ -250,6 +280,10 @@ class Solver:
                                       fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
         return fb
 
+    def free_molecular_state(self):
+        """Overwrite the state with the free-molecular steady state of the diffuse walls."""
+        _check(load().hrlb_free_molecular_state(self.handle))
+
     def set_launch(self, cells, waves):
         _check(load().hrlb_set_launch(self.handle, cells, waves))
 
@@ -275,6 +309,15 @@ class Solver:
         n = (ctypes.c_longlong * 2)()
         _check(load().hrlb_get_timing(self.handle, ms, n))
         return {'stage_ms': ms[0], 'stage_launches': n[0], 'closure_ms': ms[1], 'closure_launches': n[1]}
+
+    def get_stage_timing(self):
+        """Device time (ms) and launch counts of the stage kernel per RK3 stage and of the
+        closure kernel, accumulated since set_timing(True)."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_longlong * 4)()
+        _check(load().hrlb_get_stage_timing(self.handle, ms, n))
+        return {'stage_ms': [ms[0], ms[1], ms[2]], 'stage_launches': [n[0], n[1], n[2]], 'closure_ms': ms[3],
+                'closure_launches': n[3]}
 
     def synchronize(self):
         self.stream.synchronize()

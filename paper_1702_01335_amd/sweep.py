@@ -27,6 +27,16 @@ def sample(n, seed, kn_range=(0.01, 100.0), uw_range=(0.05, 0.6), omegas=(0.5, 0
     return out
 
 
+def smallest_cell(S, A):
+    """Width of the smallest of S cells on the half channel: the equidistant 1/(2S), or on
+    the tanh grid of Eq. stretch (x = tanh(eta) / 2A, eta_s = (s - 1/2) artanh(A) / S) the
+    cell at the wall, whose interfaces sit at eta = artanh(A) (S -+ 1/2 -+ 1/2) / S."""
+    if A == 0.0:
+        return 1.0 / (2 * S)
+    e = np.arctanh(A) / S
+    return (np.tanh(S * e) - np.tanh((S - 1) * e)) / (2 * A)
+
+
 class Sweep:
     """Groups of sampled instances on the GPU, advanced as one Batch."""
 
@@ -58,7 +68,7 @@ class Sweep:
         Qx, S = key
         q = self._quad(Qx)
         px, _ = q.nodes(0)
-        dx = 1.0 / (2 * S)   # equidistant half channel
+        dx = smallest_cell(S, self.A)
         params = []
         for i in idx:
             d = self.instances[i]
