@@ -1,0 +1,106 @@
+"""Writes the oracle-computed expected values of the long GPU parity tests (calls only the
+oracle and the seeded input generator; nothing here comes from the HIP path).
+
+    python tests/golden/make_oracle_golden.py [steady] [long]
+
+steady  couette_bgk_s64_v128 from the equilibrium start run to the steady state:
+        residual (R = ||F_{l+1} - F_l|| / (dt ||F_l||), checked every 1000 steps) below
+        1e-12, with the residual history, the decay rate of R per unit time over the last
+        checks, and the 14-moment table of the final state.  -> couette_bgk_s64_v128_steady.json
+long    couette_shakhov_s512_v3600 from the seeded start (splitmix64 seed 3, eps 0.05) after
+        100 RK3 steps: the 14-moment table, the residual of the last step, and the
+        populations of a sample of velocity columns (every x node at one (y, z) pair, and
+        every (y, z) pair at the two outermost and the innermost x node of each sign) at
+        every eighth node and the last eight.  -> couette_shakhov_s512_v3600_seed3_100steps.npz
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import solver as sv  # noqa: E402
+from paper_1702_01335_amd import inputs  # noqa: E402
+from paper_1702_01335_amd.workloads import workload  # noqa: E402
+
+
+def params_of(wl):
+    return sv.Params(Qx=wl['Qx'], Qy=wl['Qy'], Qz=wl['Qz'], S=wl['S'], scheme=wl['scheme'], **wl['params'])
+
+
+def steady(tol=1e-12, every=1000, max_steps=400000):
+    wl = workload('couette_bgk_s64_v128')
+    m = sv.Model(params_of(wl))
+    F = sv.equilibrium_state(m)
+    hist = []
+    steps = 0
+    t0 = time.time()
+    while steps < max_steps:
+        for _ in range(every - 1):
+            F = sv.rk3_step(F, m)
+        Fn = sv.rk3_step(F, m)
+        steps += every
+        R = sv.residual(Fn, F, m.p.dt)
+        F = Fn
+        hist.append([steps, R])
+        print(f"[steady] {steps} steps, R = {R:.3e} ({time.time() - t0:.0f} s)", flush=True)
+        if R < tol:
+            break
+    # decay rate of R per unit time over the last ten checks (a straight line in log R)
+    h = np.array(hist[-10:])
+    lam = -np.polyfit(h[:, 0] * m.p.dt, np.log(h[:, 1]), 1)[0]
+    out = dict(workload='couette_bgk_s64_v128', start='equilibrium at rest', tol=tol, check_every=every,
+               steps=steps, residual=R, decay_rate_per_time=lam, residual_history=hist,
+               moment_columns=['n', 'ux', 'uy', 'uz', 'T', 'Pxx', 'Pyy', 'Pzz', 'Pxy', 'Pxz', 'Pyz', 'qx', 'qy', 'qz'],
+               moments=sv.moments(F, m).table().tolist())
+    path = os.path.join(HERE, 'couette_bgk_s64_v128_steady.json')
+    with open(path, 'w') as f:
+        json.dump(out, f, indent=0)
+    print(f"[steady] wrote {path}: {steps} steps, R {R:.2e}, decay rate {lam:.4f} per unit time", flush=True)
+
+
+def sample_columns(Qx, Qy, Qz):
+    """Every x node at one (y, z) pair; every (y, z) pair at the two outermost x nodes of
+    each sign and at the innermost node of each sign."""
+    cols = set()
+    for i in range(2 * Qx):
+        cols.add((i * Qy + Qy // 2) * Qz + Qz // 3)
+    for i in (0, 1, Qx - 1, Qx, 2 * Qx - 2, 2 * Qx - 1):
+        for j in range(Qy):
+            for k in range(Qz):
+                cols.add((i * Qy + j) * Qz + k)
+    return np.array(sorted(cols))
+
+
+def long_run(steps=100, seed=3):
+    wl = workload('couette_shakhov_s512_v3600')
+    m = sv.Model(params_of(wl))
+    F = sv.seeded_state(m, inputs.perturbation(seed, (m.p.S, m.V)), 0.05)
+    t0 = time.time()
+    for n in range(steps):
+        Fprev = F
+        F = sv.rk3_step(F, m)
+        if (n + 1) % 10 == 0:
+            print(f"[long] {n + 1} steps ({time.time() - t0:.0f} s)", flush=True)
+    R = sv.residual(F, Fprev, m.p.dt)
+    S = m.p.S
+    nodes = np.array(sorted(set(range(0, S, 8)) | set(range(S - 8, S))))
+    cols = sample_columns(wl['Qx'], wl['Qy'], wl['Qz'])
+    path = os.path.join(HERE, 'couette_shakhov_s512_v3600_seed3_100steps.npz')
+    np.savez_compressed(path, steps=steps, seed=seed, eps=0.05, residual=R, nodes=nodes, cols=cols,
+                        F=F[np.ix_(nodes, cols)], col_max=np.abs(F).max(axis=0)[cols],
+                        moments=sv.moments(F, m).table())
+    print(f"[long] wrote {path}: {len(nodes)} nodes x {len(cols)} columns, R {R:.6e}", flush=True)
+
+
+if __name__ == '__main__':
+    which = sys.argv[1:] or ['steady', 'long']
+    if 'steady' in which:
+        steady()
+    if 'long' in which:
+        long_run()

@@ -9,10 +9,7 @@ here.  What holds without it, and is checked:
     order in k: the slip u_slip / u_w is positive and grows with k; L u'_y(0) / 2u_w and
     mdot / mdot_hydro lie below their hydrodynamic value 1 and fall as k grows; T_xy /
     T_xy^bal lies below its ballistic value 1 and grows with k.
-Runs only with HRLB_LONG=1 (about a minute of GPU time)."""
-import math
-import os
-
+About 30 s of GPU time."""
 import numpy as np
 import pytest
 
@@ -20,9 +17,7 @@ from oracle import diagnostics as dg
 from oracle import solver as sv
 from paper_1702_01335_amd import hrlb
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skipif(os.environ.get('HRLB_LONG') != '1',
-                                 reason='about a minute of GPU time: set HRLB_LONG=1 to run')]
+pytestmark = pytest.mark.gpu
 
 # (k, Q_x, S, dt): Table I; dt keeps max|p_x| dt / dx_min near 0.45 on each grid
 CASES = [(0.03, 4, 64, 1e-4), (0.1, 7, 32, 1.5e-4), (1.0, 21, 32, 7.5e-5)]

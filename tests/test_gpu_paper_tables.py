@@ -4,9 +4,9 @@ Tables IV, V and VI for nu, Pi and T_0; tests/golden/paper_tables.json with the 
 Argon and helium (Sutherland law with the constants given after Eq. sutherland_tau),
 kn = 1 / (delta sqrt 2), u_w = sqrt 2 and 0.1 sqrt 2, with the paper's settings: Pr = 2/3,
 S = 16 nodes stretched with A = 0.98, HHLB(6;Q_x) on x, HLB(6;7) on y, WENO-5, and Q_x and dt
-from Table III.  The paper integrates p_z out (reduced phi, chi distributions); the library
-keeps an explicit p_z axis, here with Q_z = 5 (N_z = 4, enough for the z-moments the Shakhov
-target needs).  After several diffusion times nu (Eq. vgrad), Pi (Eq. stress, with the
+from Table III.  The paper integrates p_z out (reduced phi, chi distributions); each table is
+run on the library's reduced model and with an explicit p_z axis, Q_z = 5 (N_z = 4, enough
+for the z-moments the Shakhov target needs).  After several diffusion times nu (Eq. vgrad), Pi (Eq. stress, with the
 average of Eq. Txy) and T_0 (Eq. T0) are compared with the printed values at the printed
 precision, as the oracle's own test of the tables does.  The residual is not used as the
 stopping rule: with the epsilon-free WENO-5 it settles near 1e-4 for some of these instances
@@ -30,13 +30,14 @@ pytestmark = pytest.mark.gpu
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), 'golden', 'paper_tables.json')))
 
 
-def _run_and_compare(run, deltas, steps, chunk, t0_rel=0.0):
+def _run_and_compare(run, deltas, steps, chunk, t0_rel=0.0, model='explicit'):
     """Advance one batch over (gas, delta, u_w) with the Table III settings `run` and return
     the diagnostics that miss the printed values.  Printed values are rounded to 3 decimals
     for nu and T_0 and to 4 significant digits for Pi; the allowance is that half-unit plus a
-    1e-4 margin, and for T_0 at least `t0_rel` relative."""
+    1e-4 margin, and for T_0 at least `t0_rel` relative.  model: 'explicit' (p_z on HLB(4;5))
+    or 'reduced' (the paper's own phi, chi distributions)."""
     cases = [(gas, d, uw) for uw in (math.sqrt(2), 0.1 * math.sqrt(2)) for gas in ('Ar', 'He') for d in deltas]
-    q = hrlb.Quadrature(run['Qx'], 7, 5)
+    q = hrlb.ReducedQuadrature(run['Qx'], 7) if model == 'reduced' else hrlb.Quadrature(run['Qx'], 7, 5)
     plist = [hrlb.make_params(kn=1 / (float(d) * math.sqrt(2)), dt=run['dt'], u_w=uw, pr=2 / 3, law='sutherland',
                               suth_S=GOLD['sutherland_S'][gas], A=0.98) for gas, d, uw in cases]
     s = hrlb.Solver(q, 16, 'weno5', plist)
@@ -70,14 +71,17 @@ def _run_and_compare(run, deltas, steps, chunk, t0_rel=0.0):
     return bad
 
 
-def test_gpu_reproduces_tables_IV_to_VI():
+@pytest.mark.parametrize("model", ['explicit', 'reduced'])
+def test_gpu_reproduces_tables_IV_to_VI(model):
     """delta = 1, 10, 20, 40 in one batch of 16 instances (Q_x = 7, dt = 5e-4): 120 000 steps,
-    60 time units, several diffusion times at delta = 40."""
-    bad = _run_and_compare(GOLD['table_III']['delta>=1'], ('1', '10', '20', '40'), 120000, 20000)
+    60 time units, several diffusion times at delta = 40; with p_z explicit and with the
+    paper's reduced distributions."""
+    bad = _run_and_compare(GOLD['table_III']['delta>=1'], ('1', '10', '20', '40'), 120000, 20000, model=model)
     assert not bad, bad
 
 
-def test_gpu_reproduces_tables_IV_to_VI_transition_regime():
+@pytest.mark.parametrize("model", ['explicit', 'reduced'])
+def test_gpu_reproduces_tables_IV_to_VI_transition_regime(model):
     """delta = 0.1 (Q_x = 30, dt = 2.5e-4): 240 000 steps, 60 time units; the diagnostics stop
     changing in their fifth digit after about 200 000.  nu and Pi match to the printed
     precision.  Argon's T_0 settles at 1.6453 against the printed 1.646, 4.4e-4 relative:
@@ -85,5 +89,5 @@ def test_gpu_reproduces_tables_IV_to_VI_transition_regime():
     depends on the model choice (Sec. VI, discussion of Table VI), which is the allowance
     used for T_0 here."""
     bad = _run_and_compare(GOLD['table_III']['0.1'], ('0.1',), 240000, 40000,
-                           t0_rel=GOLD['model_spread']['T0_rel'])
+                           t0_rel=GOLD['model_spread']['T0_rel'], model=model)
     assert not bad, bad

@@ -122,7 +122,7 @@ def test_bgk_s64_v128_full_size(steps):
     assert res[0] == pytest.approx(Ro, rel=1e-8)
 
 
-@pytest.mark.parametrize("steps", [1, 10])
+@pytest.mark.parametrize("steps", [1, 10, 100])
 def test_shakhov_s256_v800_full_size(steps):
     wl = workload('couette_shakhov_s256_v800')
     Fg, _, res, _ = gpu_run(wl, steps, seeds=[2])
@@ -165,6 +165,19 @@ def test_paper_maxwell_s16_v686_full_size(steps):
     Fg, _, res, _ = gpu_run(wl, steps, seeds=[5])
     Fo, m, Ro = oracle_run(wl, steps, seed=5)
     assert_parity(Fg[0], Fo, m, f"paper maxwell s16 v686 steps={steps}")
+    assert res[0] == pytest.approx(Ro, rel=1e-8)
+
+
+@pytest.mark.parametrize("k,Qx,S,dt", [(0.03, 4, 64, 1e-4), (0.1, 7, 32, 1.5e-4), (1.0, 21, 32, 7.5e-5)])
+def test_linearised_regime_table1_models(k, Qx, S, dt):
+    """The Table I models of the linearised Couette flow (Sec. IV): BGK, tau = k / sqrt 2
+    (Eq. knLuo), HHLB(N_x;Q_x) x HLB(1;2) on the phi function alone (Q_z = 1), 0.98-stretched
+    nodes, WENO-5, at u_w = 1e-3 (small, yet well above rounding), 200 steps from the seeded
+    start."""
+    wl = make_wl(Qx, 2, 1, S, 'weno5', kn=k, u_w=1e-3, pr=1.0, omega=1.0, law='lowmach', A=0.98, dt=dt)
+    Fg, _, res, _ = gpu_run(wl, 200, seeds=[13])
+    Fo, m, Ro = oracle_run(wl, 200, seed=13)
+    assert_parity(Fg[0], Fo, m, f"Table I model k={k} Qx={Qx} S={S}")
     assert res[0] == pytest.approx(Ro, rel=1e-8)
 
 
