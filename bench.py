@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
 BYTES_PER_PAIR_STEP = 64   # algorithmic: stage 1 16 B, stages 2-3 24 B each (read F_in, F_l; write F_out)
+STAGE_BYTES = (16, 24, 24)
 
 
 def parse():
@@ -43,14 +44,17 @@ def parse():
                          '(default: time every shape on this GPU)')
     ap.add_argument('--copy-probe-mib', type=int, default=0,
                     help='also run one device copy of this size (calibrates HBM byte counters under a profiler)')
-    ap.add_argument('--cpu-seconds', type=float, default=15.0)
+    ap.add_argument('--cpu-seconds', type=float, default=12.0,
+                    help='seconds of oracle stepping for each of the one-core and all-core CPU figures')
+    ap.add_argument('--cpu-cores', type=int, default=0,
+                    help='processes of the all-core CPU figure (default: the cores this process may use, at most 16)')
     ap.add_argument('--no-sweep', action='store_true', help='skip the ragged-sweep measurements')
     ap.add_argument('--sweep-instances', type=int, default=256)
     ap.add_argument('--steady-instances', type=int, default=16)
     ap.add_argument('--no-warm', action='store_true', help='skip the learned warm-start measurement')
     ap.add_argument('--no-workloads', action='store_true', help='skip the per-workload table')
-    ap.add_argument('--warm-train', type=int, default=1000, help='instances whose steady states train the network')
-    ap.add_argument('--warm-heldout', type=int, default=100)
+    ap.add_argument('--warm-train', type=int, default=2000, help='instances whose steady states train the network')
+    ap.add_argument('--warm-heldout', type=int, default=200)
     ap.add_argument('--warm-steps', type=int, default=10000, help='AdamW steps of the network')
     return ap.parse_args()
 
@@ -130,6 +134,16 @@ def sweep_section(n_inst, n_steady, steps):
         e1.synchronize()
         return e0.elapsed_time(e1) / k
 
+    # the same instances with the survey's reading of the sweep's scheme and grid (WENO-5 on
+    # the A = 0.98 tanh grid): throughput only (the epsilon-free WENO-5 residual need not
+    # fall to 1e-10, so the time to steady state is measured with upwind-2 below)
+    sw = Sweep(sample(n_inst, 20170204), scheme='weno5', A=0.98)
+    cw, ww, _ = sw.autotune(probe_steps=5)
+    ms_w = timed(sw.batch.step, steps)
+    weno = dict(scheme='weno5', A=0.98, launch=dict(cells=cw, waves=ww, graph=True), batched_ms_per_step=ms_w,
+                value=sw.pairs() / ms_w / 1e6, unit='G pair-updates/s')
+    del sw
+    torch.cuda.empty_cache()
     sw = Sweep(sample(n_inst, 20170204))
     cells, waves, _ = sw.autotune(probe_steps=5)
     pairs = sw.pairs()
@@ -154,7 +168,7 @@ def sweep_section(n_inst, n_steady, steps):
     out = dict(instances=n_inst, pairs=pairs, launch=dict(cells=cells, waves=waves, graph=True),
                batched_ms_per_step=ms_b, value=pairs / ms_b / 1e6, unit='G pair-updates/s',
                groups_one_by_one_ms_per_step=ms_g, instances_one_by_one_ms_per_step=ms_i,
-               speedup_vs_groups=ms_g / ms_b, speedup_vs_instances=ms_i / ms_b)
+               speedup_vs_groups=ms_g / ms_b, speedup_vs_instances=ms_i / ms_b, weno5_stretched=weno)
     if n_steady:
         tol, budget, every = 1e-10, 400000, 1000
         inst = sample(n_steady, 20170206, qx=(4, 8), nodes=(64,))
@@ -223,24 +237,50 @@ def warm_section(n_train, n_heldout, train_steps):
                 heldout=res)
 
 
-def cpu_baseline(wl, seconds):
-    """The oracle (numpy, FP64, single-threaded) on one instance of the workload for a
-    bounded number of steps; returns pair-updates per second."""
-    import numpy as np
+def _oracle_worker(args):
+    """Step one seeded instance of the workload with the oracle for about `seconds`;
+    returns (steps, elapsed).  Runs in its own process, single-threaded."""
+    wl, seed, seconds = args
     from oracle import solver as sv
     from paper_1702_01335_amd import inputs
     p = sv.Params(Qx=wl['Qx'], Qy=wl['Qy'], Qz=wl['Qz'], S=wl['S'], scheme=wl['scheme'], **wl['params'])
     m = sv.Model(p)
-    F = sv.seeded_state(m, inputs.perturbation(1000, (p.S, m.V)), 0.05)
+    F = sv.seeded_state(m, inputs.perturbation(seed, (p.S, m.V)), 0.05)
     F = sv.rk3_step(F, m)  # warm-up
     t0 = time.perf_counter()
     n = 0
     while time.perf_counter() - t0 < seconds or n < 2:
         F = sv.rk3_step(F, m)
         n += 1
-    dt = time.perf_counter() - t0
-    return dict(value=p.S * m.V * n / dt / 1e9, unit='G pair-updates/s', cores=1, kind='oracle',
-                sample=f"{n} RK3 steps of one instance (S={p.S}, V={m.V}) in {dt:.1f} s, numpy single thread")
+    return n, time.perf_counter() - t0
+
+
+def cpu_cores():
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail))
+
+
+def cpu_baseline(wl, seconds, cores):
+    """The oracle (numpy, FP64) on the host: one instance in one process for the one-core
+    figure, then `cores` independent instances in as many single-threaded processes for the
+    all-core figure (instances are independent, so that is how the host would run a batch).
+    Returns pair-updates per second."""
+    import multiprocessing as mp_
+    pairs = wl['S'] * 2 * wl['Qx'] * wl['Qy'] * wl['Qz']
+    n1, t1 = _oracle_worker((wl, 1000, seconds))
+    one = pairs * n1 / t1 / 1e9
+    ctx = mp_.get_context('spawn')
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(wl, 1000 + b, seconds) for b in range(cores)])
+    allc = sum(pairs * n / t for n, t in res) / 1e9
+    steps = sum(n for n, _ in res)
+    return dict(value=allc, unit='G pair-updates/s', cores=cores, kind='oracle',
+                sample=f"{cores} instances (S={wl['S']}, V={pairs // wl['S']}) in {cores} single-threaded processes, "
+                       f"{steps} RK3 steps in about {seconds:.0f} s each",
+                one_core=dict(value=one, cores=1, sample=f"{n1} RK3 steps of one instance in {t1:.1f} s"))
 
 
 def main():
@@ -270,15 +310,21 @@ def main():
     ms, wall = time_steps(solver, args.steps, args.warmup)
     value = pairs / (ms * 1e-3) / 1e9
 
-    # per-kernel device time of the same step sequence, HIP events on the solver's stream
+    # per-kernel device time of the same step sequence, HIP events on the solver's stream,
+    # per RK3 stage: stage 1 moves 16 B per pair (read F_l, write F1), stages 2 and 3 24 B
     solver.set_timing(True)
     solver.step(min(args.steps, 20))
-    tm = solver.get_timing()
+    tm = solver.get_stage_timing()
     solver.set_timing(False)
-    stage_avg_s = tm['stage_ms'] / tm['stage_launches'] * 1e-3
+    stage_s = [ms / n * 1e-3 for ms, n in zip(tm['stage_ms'], tm['stage_launches'])]
+    stage_bytes = [pairs * b for b in STAGE_BYTES]
+    stage_avg_s = sum(stage_s) / 3.0
     closure_avg_s = tm['closure_ms'] / tm['closure_launches'] * 1e-3
     bytes_per_launch = pairs * BYTES_PER_PAIR_STEP / 3.0
     achieved = bytes_per_launch / stage_avg_s
+    per_stage = [dict(stage=k + 1, avg_launch_us=stage_s[k] * 1e6, bytes_per_launch=stage_bytes[k],
+                      achieved=stage_bytes[k] / stage_s[k] / 1e9, frac=stage_bytes[k] / stage_s[k] / HBM_PEAK)
+                 for k in range(3)]
     traffic = profiled_traffic(f"stage_kernel_{args.workload}_b{args.batch}", bytes_per_launch, cells, waves)
     res = solver.residual()
 
@@ -321,8 +367,10 @@ def main():
                      'frac': achieved / HBM_PEAK,
                      'traffic': traffic['bytes_per_launch'] if traffic else None, 'traffic_unit': 'bytes/launch',
                      'traffic_detail': traffic,
-                     'kernel': 'stage_kernel', 'avg_launch_us': stage_avg_s * 1e6,
-                     'bytes_per_launch': bytes_per_launch, 'closure_avg_us': closure_avg_s * 1e6},
+                     'kernel': 'stage_kernel (the three RK3 stages; frac over their average launch)',
+                     'avg_launch_us': stage_avg_s * 1e6, 'bytes_per_launch': bytes_per_launch,
+                     'per_stage': per_stage, 'closure_avg_us': closure_avg_s * 1e6,
+                     'step_frac': pairs * BYTES_PER_PAIR_STEP / (ms * 1e-3) / HBM_PEAK},
         'single_instance': single,
         'residual_max': float(res.max()),
         'wall_s_timed': wall,
@@ -341,7 +389,7 @@ def main():
         out['warm_start'] = warm_section(args.warm_train, args.warm_heldout, args.warm_steps)
         progress(f"warm start: wall ratio {out['warm_start']['heldout']['wall_ratio']:.3f}")
     if not args.no_cpu:
-        out['cpu_baseline'] = cpu_baseline(wl, args.cpu_seconds)
+        out['cpu_baseline'] = cpu_baseline(wl, args.cpu_seconds, args.cpu_cores or cpu_cores())
     print(json.dumps(out), flush=True)
 
 
