@@ -63,7 +63,7 @@ def make_solver(wl, batch, device):
     import numpy as np
     import torch
     from paper_1702_01335_amd import hrlb, inputs
-    q = hrlb.Quadrature(wl['Qx'], wl['Qy'], wl['Qz'])
+    q = hrlb.ReducedQuadrature(wl['Qx'], wl['Qy']) if wl.get('reduced') else hrlb.Quadrature(wl['Qx'], wl['Qy'], wl['Qz'])
     S = wl['S']
     r = torch.empty((batch, S, q.V), dtype=torch.float64, device=device)
     for b in range(batch):
@@ -197,14 +197,18 @@ def workloads_section(steps, warmup):
     for name, batch in (('couette_bgk_s64_v128', 1), ('couette_bgk_s64_v128', 4096),
                         ('couette_shakhov_s256_v800', 1), ('couette_shakhov_s256_v800', 512),
                         ('couette_shakhov_s512_v3600', 1), ('couette_shakhov_s512_v3600', 64),
-                        ('paper_maxwell_s16_v686', 1), ('paper_maxwell_s16_v686', 4096)):
+                        ('paper_maxwell_s16_v686', 1), ('paper_maxwell_s16_v686', 4096),
+                        ('couette_shakhov_s256_reduced', 1), ('couette_shakhov_s256_reduced', 1024),
+                        ('paper_sutherland_s16_reduced', 1), ('paper_sutherland_s16_reduced', 8192)):
         wl = workload(name)
         q, s = make_solver(wl, batch, 'cuda:0')
         c, w, _ = s.autotune(probe_steps=3)
         s.set_graph(True)
         ms, _ = time_steps(s, steps, warmup)
         pairs = batch * wl['S'] * q.V
-        out.append(dict(workload=name, batch=batch, pairs=pairs, launch=dict(cells=c, waves=w), ms_per_step=ms,
+        out.append(dict(workload=name, batch=batch, pairs=pairs, populations_per_node=q.V,
+                        velocities_per_node=q.V // 2 if wl.get('reduced') else q.V,
+                        launch=dict(cells=c, waves=w), ms_per_step=ms,
                         value=pairs / (ms * 1e-3) / 1e9,
                         hbm_frac_step=pairs * BYTES_PER_PAIR_STEP / (ms * 1e-3) / HBM_PEAK))
         del s
