@@ -122,3 +122,47 @@ def test_bgk_target_is_plain_maxwellian():
                      np.array([1.0, 1.1]), (np.array([0.1, 0.0]), np.zeros(2), np.zeros(2)))
     FS = sv.shakhov_target(mom, m)
     assert np.array_equal(FS, m.vs.maxwellian(mom.n, *mom.u, mom.T))
+
+
+def test_compensated_dot_meets_its_published_error_bound():
+    """Dot2 (Ogita, Rump and Oishi 2005, their error bound for the twice-precision dot
+    product): |res - s| <= eps |s| + gamma_n^2 sum |c_k m_k|, gamma_n = n eps / (1 - n eps),
+    with s the exact sum of the double inputs (rational arithmetic), on the projection inputs
+    at rest and at random states, where the terms cancel to 1e-17 of their size."""
+    from fractions import Fraction
+    from oracle import equilibrium as eq
+    eps = 2.0 ** -53
+    rng = np.random.default_rng(5)
+    ax = eq.AxisProjection('half', 50, 6)
+    states = [(0.0, 1.0)] + [(rng.uniform(-0.3, 0.3), rng.uniform(0.8, 1.2)) for _ in range(6)]
+    for u, T in states:
+        M = eq.half_gaussian_moments(6, u, T)
+        J = eq.compensated_dot(ax.C, M)
+        for l in range(7):
+            exact = sum(Fraction(float(ax.C[l, k])) * Fraction(float(M[k])) for k in range(7))
+            n = l + 1
+            gam = n * eps / (1 - n * eps)
+            bound = eps * abs(float(exact)) + gam ** 2 * float(np.abs(ax.C[l] * M).sum())
+            assert abs(Fraction(float(J[l])) - exact) <= Fraction(bound), (u, T, l)
+
+
+@pytest.mark.parametrize("Q", [4, 7, 16, 50])
+def test_projected_factor_matches_exact_evaluation(Q):
+    """The float64 half-range factor against its mpmath evaluation from the rule's unrounded
+    nodes, weights and polynomials: the difference is the rounding of the tabulated
+    coefficients C_lk and of the moments I_k, amplified by the outer nodes, and stays within
+    2 eps sum_l |Phi_il| sum_k |C_lk I_k| + 2 eps |g_i| (first-order bound; measured at most
+    0.56 of it with a factor 1), at rest and at moving states; at rest and Q = 4 it is a few
+    ulp, at Q = 50 6.6e-8 relative at the outermost node."""
+    from oracle import equilibrium as eq
+    eps = 2.0 ** -53
+    ax = eq.AxisProjection('half', Q, min(6, Q - 1))
+    for u, T in ((0.0, 1.0), (0.05, 0.97), (-0.2, 1.1), (0.4, 1.3)):
+        f, e = ax.factor(u, T), ax.factor_exact(u, T)
+        for Mv, half in ((eq.half_gaussian_moments(ax.N, u, T), slice(Q, 2 * Q)),
+                         (eq.half_gaussian_moments(ax.N, -u, T), slice(Q - 1, None, -1))):
+            amp = np.abs(ax.Phi) @ (np.abs(ax.C) @ np.abs(Mv))
+            bound = 2 * eps * amp + 2 * eps * np.abs(e[half])
+            assert np.all(np.abs(f[half] - e[half]) <= bound), (u, T)
+        if Q == 4 and u == 0.0:
+            assert np.abs(f / e - 1).max() < 1e-14
