@@ -48,6 +48,8 @@ def parse():
                     help='seconds of oracle stepping for each of the one-core and all-core CPU figures')
     ap.add_argument('--cpu-cores', type=int, default=0,
                     help='processes of the all-core CPU figure (default: the cores this process may use, at most 16)')
+    ap.add_argument('--cpu-suite', action='store_true',
+                    help='only time the oracle on the host on the measurement plan\'s cases (long; no GPU use)')
     ap.add_argument('--no-sweep', action='store_true', help='skip the ragged-sweep measurements')
     ap.add_argument('--sweep-instances', type=int, default=256)
     ap.add_argument('--steady-instances', type=int, default=16)
@@ -259,6 +261,62 @@ def _oracle_worker(args):
     return n, time.perf_counter() - t0
 
 
+def _oracle_job(job):
+    """One timing job of the CPU suite, in its own single-threaded process: ('steady', wl,
+    budget) runs the workload from the equilibrium start until the residual of a step falls
+    below 1e-10 (checked every 1000 steps) or the budget is spent; ('steps', wl, n, seed)
+    runs n steps from the seeded start."""
+    from oracle import solver as sv
+    from paper_1702_01335_amd import inputs
+    kind, wl = job[0], job[1]
+    p = sv.Params(Qx=wl['Qx'], Qy=wl['Qy'], Qz=wl['Qz'], S=wl['S'], scheme=wl['scheme'], **wl['params'])
+    m = sv.Model(p)
+    t0 = time.perf_counter()
+    if kind == 'steady':
+        F, steps, R = sv.run_to_steady(sv.equilibrium_state(m), m, 1e-10, job[2], check_every=1000)
+    else:
+        F = sv.seeded_state(m, inputs.perturbation(job[3], (p.S, m.V)), 0.05)
+        for _ in range(job[2]):
+            F = sv.rk3_step(F, m)
+        steps, R = job[2], float('nan')
+    wall = time.perf_counter() - t0
+    return dict(name=wl.get('name', ''), kind=kind, S=p.S, V=m.V, steps=int(steps), residual=float(R), wall_s=wall,
+                value=p.S * m.V * steps / wall / 1e9)
+
+
+def cpu_suite(cores):
+    """The oracle's timings of the measurement plan, host only (no GPU): the first workload and
+    the paper-shape workload from the equilibrium start to residual 1e-10, the third workload
+    for 100 steps, and the 16 sweep instances of the time-to-steady comparison (seed
+    20170206, S = 64, Qx in {4, 8}, upwind-2, Courant 0.5) to 1e-10; the jobs run as
+    independent single-threaded processes on `cores` cores."""
+    import multiprocessing as mp_
+    import numpy as np
+    from oracle import quadrature as oq
+    from paper_1702_01335_amd.sweep import sample
+    from paper_1702_01335_amd.workloads import workload
+    jobs = []
+    for name, budget in (('couette_bgk_s64_v128', 400000), ('paper_maxwell_s16_v686', 200000)):
+        wl = dict(workload(name), name=name)
+        jobs.append(('steady', wl, budget))
+    jobs.append(('steps', dict(workload('couette_shakhov_s512_v3600'), name='couette_shakhov_s512_v3600'), 100, 3))
+    for k, d in enumerate(sample(16, 20170206, qx=(4, 8), nodes=(64,))):
+        dt = 0.5 * (1.0 / (2 * d['S'])) / float(np.abs(oq.x_axis(d['Qx'])[0]).max())
+        wl = dict(Qx=d['Qx'], Qy=5, Qz=5, S=d['S'], scheme='upwind2', name=f'sweep instance {k}',
+                  params=dict(kn=d['kn'], u_w=d['u_w'], omega=d['omega'], pr=2.0 / 3.0, law='power', dt=dt))
+        jobs.append(('steady', wl, 400000))
+    t0 = time.perf_counter()
+    ctx = mp_.get_context('spawn')
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_job, jobs, chunksize=1)
+    sweep = [r for r in res if r['name'].startswith('sweep')]
+    return dict(cores=cores, wall_s=time.perf_counter() - t0, jobs=[r for r in res if not r['name'].startswith('sweep')],
+                sweep_subset=dict(instances=len(sweep), converged=sum(r['residual'] < 1e-10 for r in sweep),
+                                  steps_median=float(np.median([r['steps'] for r in sweep])),
+                                  steps_max=max(r['steps'] for r in sweep),
+                                  cpu_seconds=sum(r['wall_s'] for r in sweep)))
+
+
 def cpu_cores():
     try:
         avail = len(os.sched_getaffinity(0))
@@ -289,6 +347,9 @@ def cpu_baseline(wl, seconds, cores):
 
 def main():
     args = parse()
+    if args.cpu_suite:
+        print(json.dumps({'cpu_suite': cpu_suite(args.cpu_cores or cpu_cores())}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({'error': 'one GPU only: the library drives a single device and has no multi-GPU path',
                           'n_gpus': args.gpus}))
