@@ -41,7 +41,7 @@ extern "C" {
 #define HRLB_ENOMEM (-2)   /* caller buffer smaller than hrlb_state_bytes requires        */
 #define HRLB_EHIP (-3)     /* a HIP runtime call failed; message holds hipGetErrorString  */
 #define HRLB_ENUMERIC (-4) /* n <= 0, T <= 0 or a non-finite moment met during a step, or a
-                              time step beyond the RK3 stability limit (hrlb_init_state)    */
+                              time step beyond the RK3 stability limit (hrlb_init_state)   */
 
 #define HRLB_LAW_POWER 0      /* mu = kn T^omega  -> tau = kn T^(omega-1) / n  (Eq. mw_tau for omega = 1) */
 #define HRLB_LAW_SUTHERLAND 1 /* mu = kn sqrt(T)(1+S)/(1+S/T) -> Eq. sutherland_tau with kn = 1/(delta sqrt 2) */
@@ -132,10 +132,11 @@ int hrlb_state_bytes(const hrlb_quad* q, int S, int batch, size_t* state_bytes, 
  *   A outside [0, 1), unknown law or scheme, one instance's S * V * 8 bytes not below
  *   4 GiB), HRLB_ENUMERIC (a time step beyond the stability limit of the explicit TVD RK3
  *   scheme, Eq. rk3: Courant number max|p_x| dt / min dx above 0.628 for second-order upwind
- *   or 1.434 for WENO-5 and its linear form, or dt / tau above 2.512 at the initial state
- *   (n0, T_w); the limits come from the scheme's amplification factor 1 + z + z^2/2 + z^3/6
- *   over the Fourier symbols of the linear advection operators and the negative real
- *   axis), HRLB_ENOMEM (buffers too small), HRLB_EHIP.
+ *   or 1.434 for the linear fifth-order form, the limits of the amplification factor
+ *   1 + z + z^2/2 + z^3/6 over the Fourier symbols of these linear schemes; above 2 for
+ *   WENO-5, whose nonlinear weights the paper runs at up to 1.65 (Table III), as a guard;
+ *   or dt / tau above 2.512, the limit on the negative real axis, at the initial state
+ *   (n0, T_w)), HRLB_ENOMEM (buffers too small), HRLB_EHIP.
  */
 int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* params, int batch,
                     void* d_state, size_t state_bytes, void* d_work, size_t work_bytes, void* stream,

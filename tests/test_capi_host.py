@@ -200,11 +200,12 @@ def test_step_noalloc_checks_arguments_before_device_use():
     assert e.value.code == hrlb.HRLB_EINVAL
 
 
-@pytest.mark.parametrize("scheme,dt,A,limit", [(0, 4e-3, 0.0, 0.628), (1, 8e-3, 0.0, 1.434), (1, 2e-3, 0.98, 1.434)])
+@pytest.mark.parametrize("scheme,dt,A,limit", [(0, 4e-3, 0.0, 0.628), (2, 4e-3, 0.0, 1.434), (1, 8e-3, 0.0, 2.0),
+                                              (1, 2e-3, 0.98, 2.0)])
 def test_time_step_beyond_the_rk3_stability_limit_is_refused(scheme, dt, A, limit):
     """A time step whose Courant number max|p_x| dt / min dx exceeds the RK3 limit of the
-    scheme (0.628 upwind-2, 1.434 WENO-5), or with dt / tau above 2.512, is a numerical error
-    reported before any device use."""
+    linear schemes (0.628 upwind-2, 1.434 linear fifth order) or the guard of WENO-5 (2), or
+    with dt / tau above 2.512, is a numerical error reported before any device use."""
     q = hrlb.Quadrature(8, 4, 4)
     p, _ = q.nodes(0)
     S = 64

@@ -12,8 +12,10 @@ precision, as the oracle's own test of the tables does.  The residual is not use
 stopping rule: with the epsilon-free WENO-5 it settles near 1e-4 for some of these instances
 while the diagnostics are converged to all printed digits.
 
-delta = 0.01 (Q_x = 100) is left out: it needs about 10^6 steps to settle to the printed
-digits, too long for a test."""
+delta = 0.01 (Q_x = 100, 1 000 000 steps, ~1 min) runs on the reduced model only: its 2800
+populations per node take a third of the explicit set's 7000.  At this rarefaction the
+diagnostics settle slowly (T_0 still rises by ~5e-5 per 100 000 steps at 800 000), but within
+the printed precision."""
 import json
 import math
 import os
@@ -90,4 +92,13 @@ def test_gpu_reproduces_tables_IV_to_VI_transition_regime(model):
     used for T_0 here."""
     bad = _run_and_compare(GOLD['table_III']['0.1'], ('0.1',), 240000, 40000,
                            t0_rel=GOLD['model_spread']['T0_rel'], model=model)
+    assert not bad, bad
+
+
+def test_gpu_reproduces_tables_IV_to_VI_near_free_molecular():
+    """delta = 0.01 (Q_x = 100, dt = 2.5e-4), the paper's reduced model: 1 000 000 steps,
+    250 time units.  nu, Pi and T_0 at u_w = sqrt 2 and Pi at 0.1 sqrt 2 to the printed
+    precision (T_0 within the 0.1 % model spread, as at delta = 0.1)."""
+    bad = _run_and_compare(GOLD['table_III']['0.01'], ('0.01',), 1000000, 200000,
+                           t0_rel=GOLD['model_spread']['T0_rel'], model='reduced')
     assert not bad, bad
