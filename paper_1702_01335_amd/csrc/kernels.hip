@@ -60,7 +60,7 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
 // as 6 f_q and the indicators as 12 s_q, so every coefficient is a small integer; the
 // weights (d_q / s_q^2) / sum_r (d_r / s_r^2) do not change under a common factor of the
 // indicators.  They are evaluated as N_q / sum N with N_q = d_q prod_{r != q} t_r^2, the
-// ideal weights d as 1 : 6 : 3 and t_q = s_q / 2^e, 2^e the binade of max s: one division,
+// ideal weights d as 1 : 6 : 3 and t_q = s_q / 2^e, 2^e the binade of max s: one quotient,
 // exact power-of-two scaling (so the scheme stays homogeneous of degree one), and vanishing
 // indicators give the Table II rows directly (one vanishing: N_q alone survives; two: the
 // sum vanishes and the pair row is taken; three: ideal weights).
@@ -75,14 +75,26 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
   const double s2 = 13.0 * r2 * r2 + 3.0 * q2 * q2;
   const double s3 = 13.0 * r3 * r3 + 3.0 * q3 * q3;
   const double smax = fmax(s1, fmax(s2, s3));
-  if (smax == 0.0) return (f1 + 6.0 * f2 + 3.0 * f3) * (1.0 / 60.0);
   int ex;
-  (void)frexp(smax, &ex);
+  (void)frexp(smax, &ex);  // 0 for smax = 0: then every t_q is 0
   const double t1 = ldexp(s1, -ex), t2 = ldexp(s2, -ex), t3 = ldexp(s3, -ex);
   const double u1 = t1 * t1, u2 = t2 * t2, u3 = t3 * t3;
   const double n1 = u2 * u3, n2 = 6.0 * (u1 * u3), n3 = 3.0 * (u1 * u2);
   const double den = n1 + n2 + n3;
-  if (den > 0.0) return (n1 * f1 + n2 * f2 + n3 * f3) / (6.0 * den);
+  const double num = n1 * f1 + n2 * f2 + n3 * f3;
+  // one branch on the common path.  Above 2^-1000 the quotient is num times the
+  // reciprocal of 6 den refined by two Newton steps and a final residual correction
+  // (v_rcp_f64 has no range trouble there); the few lanes below take the division itself
+  if (den > 0x1p-1000) {
+    const double x = 6.0 * den;
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    const double q = num * r;
+    return fma(r, fma(-x, q, num), q);
+  }
+  if (den > 0.0) return num / (6.0 * den);
+  if (smax == 0.0) return (f1 + 6.0 * f2 + 3.0 * f3) * (1.0 / 60.0);
   if (u1 == 0.0 && u2 == 0.0) return (f1 + 6.0 * f2) * (1.0 / 42.0);
   if (u1 == 0.0 && u3 == 0.0) return (f1 + 3.0 * f3) * (1.0 / 24.0);
   return (2.0 * f2 + f3) * (1.0 / 18.0);
@@ -677,17 +689,20 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
     else
       tau = p_kn * M_SQRT1_2;  // linearised (low Mach) regime, Eq. knLuo: tau = k / sqrt(2)
     const double invtau = (p_cl != 0.0 || bad) ? 0.0 : 1.0 / tau;
-    const double Cs = (1.0 - p_pr) / (n * T * T);
+    // Shakhov factor (Eq. sdef) S = (1 - Pr) (xi^2 / 5T - 1) xi.q / (n T^2), kept as
+    // (xi^2 - 5T) xi.q' with q' = (1 - Pr) q / (5 n T^3); q' = 0 for Pr = 1 (BGK)
+    // (zero at a node that failed the checks, whose populations then stay finite)
+    const double a_sh = bad ? 0.0 : (1.0 - p_pr) / (n * T * T * (5.0 * T));
     const auto rec = gmem(d.rec + (size_t)g * sh.rec_len);
     rec[0] = ux;
     rec[1] = uy;
     rec[2] = uz;
     rec[3] = p_dt * invtau;
-    rec[4] = Cs;
-    rec[5] = Cs / (5.0 * T);
-    rec[6] = qx;
-    rec[7] = qy;
-    rec[8] = qz;
+    rec[4] = bad ? 0.0 : 5.0 * T;
+    rec[5] = 0.0;
+    rec[6] = a_sh * qx;
+    rec[7] = a_sh * qy;
+    rec[8] = a_sh * qz;
     rec[9] = p_dt * p_idx;
     // projection coefficients of the 1D Maxwellian factors (Sec. III)
     double a[NYZ_MAX + 1];
@@ -872,8 +887,8 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   // reduced Shakhov factors (Eq. sred_def): integrating (xi^2 / 5T - 1) over p_z against the
   // Maxwellian leaves xi_perp^2 / 5T - 4/5 for phi and xi_perp^2 / 5T - 2/5 for chi (the
   // p_z^2 and p_z^4 moments T and 3 T^2), so the constant term of Eq. sdef is scaled by
-  // 4/5 or 2/5
-  const double cmul = RED ? (k == 0 ? 0.8 : 0.4) : 1.0;
+  // 4/5 or 2/5 (negated here: the factor is formed as xi_perp^2 + cneg 5T)
+  const double cneg = RED ? (k == 0 ? -0.8 : -0.4) : -1.0;
   const bool pos = px > 0.0;
   const int vm = ((2 * Qx - 1 - i) * sh.Qy + (sh.Qy - 1 - j)) * sh.Qz + k;  // bounce-back partner
   const size_t base = (size_t)b * S * V;
@@ -918,7 +933,7 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   // the node's closure scalars (record head: u, dt / tau, the two Shakhov coefficients, q,
   // dt / dx), wave-uniform, read by scalar loads
   struct Sc {
-    double ux, uy, uz, itau, cs, a, qx, qy, qz, idx;
+    double ux, uy, uz, itau, t5, unused, qx, qy, qz, idx;
   };
   typedef __attribute__((address_space(4))) const double cdouble;
   const int clast = s0 + nloc - 1;
@@ -945,6 +960,7 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
     o = Sc{r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], r[8], r[9]};
   };
   double rd = 0.0, rf = 0.0;
+  const double act = active ? 1.0 : 0.0;
   // one node: complete the window, flux, collision, RK combine, store; returns F_out
   auto node = [&](int c, const Far& o, const Near& p, const Sc& z, bool valid) -> double {
     const double Wn = ghost_node(o.raw, c + 3, S, pos, W5, W4, W3, ex, ghost_in);
@@ -959,21 +975,21 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
     fl = fr;
     const double F = W2;
     const double feq = p.gx * p.gyz;
-    double FS = feq;
-    if (z.cs != 0.0) {
-      if constexpr (RED) {
-        (void)pz;
-        const double xx = px - z.ux, xy = py - z.uy;
-        const double xi2 = xx * xx + xy * xy;
-        const double qxi = z.qx * xx + z.qy * xy;
-        FS = feq + feq * ((z.a * xi2 - z.cs * cmul) * qxi);  // phi^eq (1 + S_phi), T phi^eq (1 + S_chi)
-      } else {
-        (void)cmul;
-        const double xx = px - z.ux, xy = py - z.uy, xz = pz - z.uz;
-        const double xi2 = xx * xx + xy * xy + xz * xz;
-        const double qxi = z.qx * xx + z.qy * xy + z.qz * xz;
-        FS = feq + feq * ((z.a * xi2 - z.cs) * qxi);  // F^eq (1 + S), Eq. sdef
-      }
+    // F^eq (1 + S), Eq. sdef, with S = (xi^2 - 5T) xi.q' (the record holds 5T and q'); no
+    // branch for BGK, whose q' = 0 gives FS = F^eq exactly
+    double FS;
+    if constexpr (RED) {
+      (void)pz;
+      const double xx = px - z.ux, xy = py - z.uy;
+      const double xi2 = xx * xx + xy * xy;
+      const double qxi = z.qx * xx + z.qy * xy;
+      FS = feq + feq * (fma(cneg, z.t5, xi2) * qxi);  // phi^eq (1 + S_phi), T phi^eq (1 + S_chi)
+    } else {
+      (void)cneg;
+      const double xx = px - z.ux, xy = py - z.uy, xz = pz - z.uz;
+      const double xi2 = xx * xx + xy * xy + xz * xz;
+      const double qxi = z.qx * xx + z.qy * xy + z.qz * xz;
+      FS = feq + feq * ((xi2 - z.t5) * qxi);
     }
     const double G = F + (FS - F) * z.itau - D;  // F + dt L[F], Eq. L_def
     double out;
@@ -983,12 +999,11 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
       out = 0.75 * o.fl0 + 0.25 * G;
     } else {
       // F_{l+1} = F_l / 3 + 2 G / 3, with the step's change F_{l+1} - F_l formed directly;
-      // the residual sums take active lanes of the chunk's nodes only (vf is uniform)
+      // the residual sums take lanes below V at the chunk's nodes only (weight w = 1, else 0)
       const double dlt = (2.0 / 3.0) * (G - o.fl0);
       out = o.fl0 + dlt;
-      const double vf = valid ? 1.0 : 0.0;
-      const double dm = active ? dlt * vf : 0.0;
-      const double flm = active ? o.fl0 * vf : 0.0;
+      const double w = act * (valid ? 1.0 : 0.0);  // the condition is uniform: no select per lane
+      const double dm = dlt * w, flm = o.fl0 * w;
       rd += dm * dm;
       rf += flm * flm;
       // keep each node's update here: sunk to the end of the 16-node group, the updates
@@ -996,8 +1011,9 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
       asm volatile("" : "+v"(rd), "+v"(rf));
     }
     // nodes past the chunk's end give finite values (clamped loads) that are neither
-    // stored nor summed
-    return active ? out : 0.0;
+    // stored nor summed; so do lanes past V (velocity V - 1), whose moment multipliers
+    // are zero
+    return out;
   };
   Far far[PIPE];
   Near near[PIPE];
