@@ -1,7 +1,7 @@
 """Writes the oracle-computed expected values of the long GPU parity tests (calls only the
 oracle and the seeded input generator; nothing here comes from the HIP path).
 
-    python tests/golden/make_oracle_golden.py [steady] [long]
+    python tests/golden/make_oracle_golden.py [steady] [long] [warm]
 
 steady  couette_bgk_s64_v128 from the equilibrium start run to the steady state:
         residual (R = ||F_{l+1} - F_l|| / (dt ||F_l||), checked every 1000 steps) below
@@ -12,6 +12,10 @@ long    couette_shakhov_s512_v3600 from the seeded start (splitmix64 seed 3, eps
         populations of a sample of velocity columns (every x node at one (y, z) pair, and
         every (y, z) pair at the two outermost and the innermost x node of each sign) at
         every eighth node and the last eight.  -> couette_shakhov_s512_v3600_seed3_100steps.npz
+warm    the two held-out instances of the warm-start GPU test (Qx = 4, Qy = Qz = 4, S = 16,
+        upwind-2, Pr = 2/3, equidistant grid, dt at Courant 0.5 on the cell 1/(2S) and the
+        largest |p_x| of the oracle's own velocity set) from the equilibrium start to
+        R < 1e-12: moments, steps and the decay rate of R.  -> warm_start_s16_steady.json
 """
 import json
 import os
@@ -98,9 +102,53 @@ def long_run(steps=100, seed=3):
     print(f"[long] wrote {path}: {len(nodes)} nodes x {len(cols)} columns, R {R:.6e}", flush=True)
 
 
+# held-out instances of the warm-start test: kn, u_w and omega inside the range its network
+# is trained on (kn 0.05..5, u_w 0.05..0.6, omega of the power law)
+WARM_INSTANCES = [dict(kn=0.2, u_w=0.3, omega=0.5), dict(kn=2.0, u_w=0.5, omega=0.81)]
+
+
+def warm(tol=1e-12, every=200, max_steps=400000):
+    S, Q = 16, 4
+    out = dict(grid=dict(Qx=Q, Qy=Q, Qz=Q, S=S, scheme='upwind2', pr=2.0 / 3.0, A=0.0, courant=0.5),
+               tol=tol, check_every=every, instances=[], steps=[], residual=[], decay_rate_per_time=[],
+               moments=[], moment_columns=['n', 'ux', 'uy', 'uz', 'T', 'Pxx', 'Pyy', 'Pzz', 'Pxy', 'Pxz', 'Pyz',
+                                           'qx', 'qy', 'qz'])
+    for inst in WARM_INSTANCES:
+        probe = sv.Model(sv.Params(Qx=Q, Qy=Q, Qz=Q, S=S, dt=1.0, scheme='upwind2', pr=2.0 / 3.0, **inst))
+        dt = 0.5 * (1.0 / (2 * S)) / float(np.abs(probe.vs.px).max())
+        m = sv.Model(sv.Params(Qx=Q, Qy=Q, Qz=Q, S=S, dt=dt, scheme='upwind2', pr=2.0 / 3.0, **inst))
+        F = sv.equilibrium_state(m)
+        hist, steps = [], 0
+        t0 = time.time()
+        while steps < max_steps:
+            for _ in range(every - 1):
+                F = sv.rk3_step(F, m)
+            Fn = sv.rk3_step(F, m)
+            steps += every
+            R = sv.residual(Fn, F, dt)
+            F = Fn
+            hist.append([steps, R])
+            if R < tol:
+                break
+        h = np.array(hist[-10:])
+        lam = -np.polyfit(h[:, 0] * dt, np.log(h[:, 1]), 1)[0]
+        print(f"[warm] {inst}: {steps} steps, R {R:.2e}, decay rate {lam:.4f} ({time.time() - t0:.0f} s)", flush=True)
+        out['instances'].append(dict(inst))
+        out['steps'].append(steps)
+        out['residual'].append(R)
+        out['decay_rate_per_time'].append(lam)
+        out['moments'].append(sv.moments(F, m).table().tolist())
+    path = os.path.join(HERE, 'warm_start_s16_steady.json')
+    with open(path, 'w') as f:
+        json.dump(out, f, indent=0)
+    print(f"[warm] wrote {path}", flush=True)
+
+
 if __name__ == '__main__':
-    which = sys.argv[1:] or ['steady', 'long']
+    which = sys.argv[1:] or ['steady', 'long', 'warm']
     if 'steady' in which:
         steady()
     if 'long' in which:
         long_run()
+    if 'warm' in which:
+        warm()

@@ -75,8 +75,14 @@ def test_gradient_matches_oracle(M):
     assert abs(loss.item() - Lo) <= 1e-3 * Lo
     for k, (a, b) in enumerate(zip(g, go)):
         err = rel(a, b)
-        print(f"[mlp]   param {k} {b.shape}: rel err {err:.2e}", flush=True)
+        # element by element, against the tensor's largest entry: the two sides round to
+        # bfloat16 at the same points but accumulate in different orders (float32 on the
+        # matrix cores, float64 in the oracle), so a rounded product can land one bfloat16
+        # step (2^-8 relative) apart and carry that into the sums downstream
+        emax = np.abs(np.asarray(a, dtype=np.float64) - b).max() / np.abs(b).max()
+        print(f"[mlp]   param {k} {b.shape}: rel err {err:.2e}, largest entry difference {emax:.2e}", flush=True)
         assert err <= 1e-2, k
+        assert emax <= 1e-2, k
     # and close to the exact float64 gradient (bfloat16 rounding only)
     _, ge = om.loss_and_grad(params, X.astype(np.float64), T.astype(np.float64), quant=False)
     for a, b in zip(g, ge):
