@@ -270,3 +270,28 @@ def test_autotune_picks_a_valid_shape_and_caches_it(tmp_path):
     Fg, _, _, _ = gpu_run(wl, 3, seeds=[43], launch=(c, w))
     Fo, m, _ = oracle_run(wl, 3, seed=43)
     assert_parity(Fg[0], Fo, m, f"tuned cells={c} waves={w}")
+
+
+def test_piecewise_flat_profile_meets_every_weno_row():
+    """A state that is flat in x on two stretches joined by a jump, then a linear ramp and a
+    third flat stretch: the WENO-5 stencils meet three vanishing smoothness indicators (the
+    ideal weights), two (the pair rows of Table II), one and none (App. A.3, Eq.
+    weno5_omega without epsilon).  One RK3 step from the same state on the GPU and in the
+    oracle, column by column.  The profile scales the oracle's equilibrium at rest, so each
+    flat stretch holds the same doubles at every node."""
+    import torch
+    wl = make_wl(4, 4, 4, 40, 'weno5', A=0.0, dt=2e-4)
+    m = sv.Model(__import__('parity').oracle_params(wl))
+    prof = np.ones(40)
+    prof[12:24] = 1.25
+    prof[24:32] = 1.25 - 0.02 * np.arange(1, 9)
+    prof[32:] = prof[31]
+    F0 = sv.equilibrium_state(m) * prof[:, None]
+    _, _, _, s = gpu_run(wl, 0)
+    s.set_state(torch.from_numpy(F0[None]).cuda())
+    s.step(1)
+    Fg = s.get_state().cpu().numpy()[0]
+    Fo = sv.rk3_step(F0, m)
+    assert_parity(Fg, Fo, m, 'piecewise flat profile, 1 step')
+    # the flat stretches far from the jump and the ramp stay exactly flat on both sides
+    assert np.array_equal(Fg[2], Fg[6]) and np.array_equal(Fo[2], Fo[6])
