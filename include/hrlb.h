@@ -74,6 +74,18 @@ typedef struct hrlb_batch hrlb_batch;
 const char* hrlb_last_error(void);
 
 /*
+ * trace_status -- whether the library emits roctx ranges.  With HRLB_TRACE set to anything
+ * but "" or "0" when the library is first used, and the roctx library
+ * (librocprofiler-sdk-roctx) loadable, every call below that enqueues work pushes a range
+ * named after itself ("hrlb_step", "hrlb_moments", ...), each RK3 step replayed from its
+ * graph one more ("RK3 step (graph launch)"), and an eager step one per launch ("closure",
+ * "RK3 stage 1".."3"); a rocprofv3 --marker-trace run shows them beside the kernels.  The
+ * ranges cover the host-side enqueue, not the kernels' execution.  *enabled = 1 when ranges
+ * are emitted, else 0.  Errors: HRLB_EINVAL for a NULL pointer.
+ */
+int hrlb_trace_status(int* enabled);
+
+/*
  * init_quadrature -- host-side velocity set and Hermite projection tables (Sec. III:
  * HHLB(Nx;Qx) x HLB(Ny;Qy), here with a third full-range factor HLB(Nz;Qz) on z).
  *   Qx: nodes per x semi-axis, 1..128; Nx: half-range expansion order, 0..min(Qx-1, 8)

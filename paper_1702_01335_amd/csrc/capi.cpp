@@ -5,9 +5,12 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <sstream>
@@ -183,9 +186,55 @@ static int default_waves(const Shape& sh) {
   return best;
 }
 
+// Optional roctx ranges around the library's calls (HRLB_TRACE=1 in the environment when the
+// library is first used): they name the host-side interval of each call, the enqueue of a
+// step and of each stage, in a rocprofv3 --marker-trace timeline beside the kernels those
+// calls launch.  The roctx library is opened at run time, so without the variable, or
+// without the library, nothing changes and nothing is linked.
+namespace {
+struct Trace {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+  bool on = false;
+  Trace() {
+    const char* e = std::getenv("HRLB_TRACE");
+    if (!e || !*e || std::strcmp(e, "0") == 0) return;
+    void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) h = dlopen("librocprofiler-sdk-roctx.so", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return;
+    push = reinterpret_cast<int (*)(const char*)>(dlsym(h, "roctxRangePushA"));
+    pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+    on = push && pop;
+  }
+};
+Trace& trace() {
+  static Trace t;
+  return t;
+}
+// one range for the lifetime of the object (pushed and popped on the calling thread)
+struct Range {
+  bool on;
+  explicit Range(const char* name) : on(trace().on) {
+    if (on) trace().push(name);
+  }
+  ~Range() {
+    if (on) trace().pop();
+  }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+const char* const STAGE_RANGE[3] = {"RK3 stage 1", "RK3 stage 2", "RK3 stage 3"};
+}  // namespace
+
 extern "C" {
 
 const char* hrlb_last_error(void) { return g_err.c_str(); }
+
+int hrlb_trace_status(int* enabled) {
+  if (!enabled) return fail(HRLB_EINVAL, "trace_status: enabled is NULL");
+  *enabled = trace().on ? 1 : 0;
+  return HRLB_OK;
+}
 
 int hrlb_init_quadrature(int Qx, int Nx, int Qy, int Ny, int Qz, int Nz, hrlb_quad** out) {
   if (!out) return fail(HRLB_EINVAL, "init_quadrature: out is NULL");
@@ -413,6 +462,7 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
                     double eps, hrlb_sim** out) {
   if (!out) return fail(HRLB_EINVAL, "init_state: out is NULL");
   *out = nullptr;
+  Range r_call("hrlb_init_state");
   if (!q || !params || !d_state || !d_work) return fail(HRLB_EINVAL, "init_state: NULL argument");
   int rc = check_instances("init_state", S, scheme, params, batch);
   if (rc != HRLB_OK) return rc;
@@ -465,6 +515,7 @@ int hrlb_step_noalloc(const hrlb_quad* q, int S, int scheme, const hrlb_params* 
                       size_t state_bytes, int nsteps, double* d_moments, void* stream) {
   if (!q || !params || !d_state) return fail(HRLB_EINVAL, "step_noalloc: NULL argument");
   if (nsteps < 0) return fail(HRLB_EINVAL, "step_noalloc: nsteps must be >= 0");
+  Range r_call("hrlb_step_noalloc");
   int rc = check_instances("step_noalloc", S, scheme, params, batch);
   if (rc != HRLB_OK) return rc;
   if ((uintptr_t)d_state & 255) return fail(HRLB_EINVAL, "step_noalloc: state buffer must be 256-byte aligned");
@@ -576,6 +627,7 @@ static hipError_t capture_step(hrlb_sim* s) {
 int hrlb_step(hrlb_sim* s, int nsteps) {
   if (!s) return fail(HRLB_EINVAL, "step: sim is NULL");
   if (nsteps < 0) return fail(HRLB_EINVAL, "step: nsteps must be >= 0");
+  Range r_call("hrlb_step");
   const Shape& sh = s->sh;
   DevPtrs& d = s->d;
   const int nvb = (sh.V + 64 * s->waves - 1) / (64 * s->waves);
@@ -596,6 +648,7 @@ int hrlb_step(hrlb_sim* s, int nsteps) {
       if (e != hipSuccess) return hip_fail(e, "step: graph capture");
     }
     for (; n < nsteps; ++n) {
+      Range r_step("RK3 step (graph launch)");
       hipError_t e = hipGraphLaunch(s->gexec, s->stream);
       if (e != hipSuccess) return hip_fail(e, "step: graph launch");
       s->resid_nres = nvb * nch;
@@ -608,11 +661,17 @@ int hrlb_step(hrlb_sim* s, int nsteps) {
       double* Fout = d.F[stage % 3];  // stage 1 -> F[1], 2 -> F[2], 3 -> F[0] (in place over F_l)
       hipEvent_t e0 = nullptr;
       hipError_t e = ev_begin(s, &e0);
-      if (e == hipSuccess) e = (hipError_t)launch_closure(sh, d, Fin, s->part_nvb, nullptr, s->stream);
+      {
+        Range r_cl("closure");
+        if (e == hipSuccess) e = (hipError_t)launch_closure(sh, d, Fin, s->part_nvb, nullptr, s->stream);
+      }
       if (e == hipSuccess) e = ev_end(s, e0, 3);
       if (e == hipSuccess) e = ev_begin(s, &e0);
-      if (e == hipSuccess)
-        e = (hipError_t)launch_stage(sh, d, stage, Fin, d.F[0], Fout, s->cells, s->waves, s->stream);
+      {
+        Range r_st(STAGE_RANGE[stage - 1]);
+        if (e == hipSuccess)
+          e = (hipError_t)launch_stage(sh, d, stage, Fin, d.F[0], Fout, s->cells, s->waves, s->stream);
+      }
       if (e == hipSuccess) e = ev_end(s, e0, stage - 1);
       if (e != hipSuccess) return hip_fail(e, "step: launch");
       s->part_nvb = nvb;
@@ -654,6 +713,7 @@ int hrlb_autotune(hrlb_sim* s, int probe_steps, const char* cache_path, int* bes
                   double* best_ms) {
   if (!s || !best_cells || !best_waves || !best_ms) return fail(HRLB_EINVAL, "autotune: NULL argument");
   if (probe_steps < 1) return fail(HRLB_EINVAL, "autotune: probe_steps must be >= 1");
+  Range r_call("hrlb_autotune");
   const std::string key = tune_key(s->sh);
   int c = 0, w = 0;
   if (tune_lookup(cache_path, key, &c, &w)) {
@@ -960,6 +1020,7 @@ int hrlb_batch_step(hrlb_batch* bt, int nsteps) {
   if (!bt) return fail(HRLB_EINVAL, "batch_step: batch is NULL");
   if (nsteps < 0) return fail(HRLB_EINVAL, "batch_step: nsteps must be >= 0");
   if (nsteps == 0) return HRLB_OK;
+  Range r_call("hrlb_batch_step");
   if (!bt->gexec) {
     hipError_t e = hipSuccess;
     if (!bt->cap_stream) e = hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking);
@@ -982,7 +1043,10 @@ int hrlb_batch_step(hrlb_batch* bt, int nsteps) {
       HIP_TRY((hipError_t)launch_partials(sm->sh, sm->d, sm->d.F[0], bt->cells, bt->waves, bt->stream),
               "batch_step: partials");
   }
-  for (int n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(bt->gexec, bt->stream), "batch_step: graph launch");
+  for (int n = 0; n < nsteps; ++n) {
+    Range r_step("batched RK3 step (graph launch)");
+    HIP_TRY(hipGraphLaunch(bt->gexec, bt->stream), "batch_step: graph launch");
+  }
   for (hrlb_sim* sm : bt->sims) {
     const int nvb = (sm->sh.V + 64 * bt->waves - 1) / (64 * bt->waves), nch = (sm->sh.S + bt->cells - 1) / bt->cells;
     sm->part_nvb = nvb;
@@ -993,6 +1057,7 @@ int hrlb_batch_step(hrlb_batch* bt, int nsteps) {
 
 int hrlb_batch_residual(hrlb_batch* bt, double* h_out) {
   if (!bt || !h_out) return fail(HRLB_EINVAL, "batch_residual: NULL argument");
+  Range r_call("hrlb_batch_residual");
   std::vector<int> flags(bt->active.size());
   for (size_t k = 0; k < bt->sims.size(); ++k) {
     hrlb_sim* sm = bt->sims[k];
@@ -1042,6 +1107,7 @@ int hrlb_set_graph(hrlb_sim* s, int on) {
 
 int hrlb_moments(hrlb_sim* s, double* d_out) {
   if (!s || !d_out) return fail(HRLB_EINVAL, "moments: NULL argument");
+  Range r_call("hrlb_moments");
   hipError_t e = (hipError_t)launch_partials(s->sh, s->d, s->d.F[0], s->cells, s->waves, s->stream);
   if (e == hipSuccess) {
     s->part_nvb = (s->sh.V + 64 * s->waves - 1) / (64 * s->waves);
@@ -1053,6 +1119,7 @@ int hrlb_moments(hrlb_sim* s, double* d_out) {
 
 int hrlb_residual(hrlb_sim* s, double* h_out) {
   if (!s || !h_out) return fail(HRLB_EINVAL, "residual: NULL argument");
+  Range r_call("hrlb_residual");
   const int B = s->sh.B;
   if (s->resid_nres > 0) {
     hipError_t e = (hipError_t)launch_residual(s->sh, s->d, s->resid_nres, s->stream);
@@ -1076,6 +1143,7 @@ int hrlb_get_state(hrlb_sim* s, double* d_out) {
 
 int hrlb_set_state(hrlb_sim* s, const double* d_in) {
   if (!s || !d_in) return fail(HRLB_EINVAL, "set_state: NULL argument");
+  Range r_call("hrlb_set_state");
   const size_t bytes = (size_t)s->sh.B * s->sh.S * s->sh.V * sizeof(double);
   HIP_TRY(hipMemcpyAsync(s->d.F[0], d_in, bytes, hipMemcpyDeviceToDevice, s->stream), "set_state: copy");
   hipError_t e = (hipError_t)launch_partials(s->sh, s->d, s->d.F[0], s->cells, s->waves, s->stream);
@@ -1099,6 +1167,7 @@ int hrlb_free_molecular_state(hrlb_sim* s) {
 int hrlb_seed_state(hrlb_sim* s, const double* d_table, int preserve_mass, int* h_fallback) {
   if (!s || !d_table) return fail(HRLB_EINVAL, "seed_state: NULL argument");
   if (s->sh.reduced) return fail(HRLB_EINVAL, "seed_state: not available for the reduced (phi, chi) model");
+  Range r_call("hrlb_seed_state");
   hipError_t e = (hipError_t)launch_seed(s->sh, s->d, d_table, preserve_mass ? 1 : 0, s->stream);
   if (e != hipSuccess) return hip_fail(e, "seed_state: launch");
   if (h_fallback)

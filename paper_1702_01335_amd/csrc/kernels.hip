@@ -930,8 +930,8 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   struct Near {
     double gx, gyz;
   };
-  // the node's closure scalars (record head: u, dt / tau, the two Shakhov coefficients, q,
-  // dt / dx), wave-uniform, read by scalar loads
+  // the node's closure scalars (record head: u, dt / tau, 5T, unused, the scaled heat flux
+  // q', dt / dx), wave-uniform, read by scalar loads
   struct Sc {
     double ux, uy, uz, itau, t5, unused, qx, qy, qz, idx;
   };

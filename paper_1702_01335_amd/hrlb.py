@@ -26,7 +26,7 @@ EXPORTS = ('hrlb_last_error', 'hrlb_init_quadrature', 'hrlb_quad_free', 'hrlb_qu
            'hrlb_set_timing', 'hrlb_get_timing', 'hrlb_batch_bytes', 'hrlb_batch_create', 'hrlb_batch_step',
            'hrlb_batch_residual', 'hrlb_batch_set_active', 'hrlb_batch_info', 'hrlb_batch_free', 'hrlb_seed_state',
            'hrlb_step_noalloc', 'hrlb_free_molecular_state', 'hrlb_get_stage_timing',
-           'hrlb_init_quadrature_reduced')
+           'hrlb_init_quadrature_reduced', 'hrlb_trace_status')
 SCRATCH_BYTES = 32 << 20  # HRLB_SCRATCH_BYTES
 
 
@@ -67,6 +67,7 @@ def load():
     vp, dp, ip, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_size_t
     lib.hrlb_last_error.restype = ctypes.c_char_p
     lib.hrlb_last_error.argtypes = []
+    lib.hrlb_trace_status.argtypes = [ip]
     lib.hrlb_init_quadrature.argtypes = [ctypes.c_int] * 6 + [ctypes.POINTER(vp)]
     lib.hrlb_init_quadrature_reduced.argtypes = [ctypes.c_int] * 4 + [ctypes.POINTER(vp)]
     lib.hrlb_quad_free.argtypes = [vp]
@@ -117,6 +118,13 @@ def _check(rc):
 
 
 # ---- the C ABI under its own names -----------------------------------------------------
+
+def trace_status():
+    """True when the library emits roctx ranges (HRLB_TRACE set when it was first used)."""
+    on = ctypes.c_int(0)
+    _check(load().hrlb_trace_status(ctypes.byref(on)))
+    return bool(on.value)
+
 
 def init_quadrature(Qx, Nx, Qy, Ny, Qz, Nz):
     h = ctypes.c_void_p()
