@@ -797,10 +797,12 @@ static inline size_t closure_lds_doubles(const Shape& sh, int nb) {
          (size_t)(sh.Nx + 1) * (sh.Nx + 1);
 }
 
-// nodes per closure block: up to 64, fewer when there are few nodes, so the grid keeps
-// several thousand blocks
+// nodes per closure block: 16, fewer when there are few nodes, so the grid keeps several
+// thousand blocks.  Timed on the benchmark batch (65 536 nodes) and on the reduced model's
+// (262 144 nodes): 16 is the fastest on both (8, 32 and 64 take 1.05-1.37x and 1.09-1.47x
+// as long; a block of 64 nodes needs 27 KB of LDS, five blocks per CU)
 static inline int closure_nodes_per_block(int total_nodes) {
-  int nb = CL_NODES;
+  int nb = 16;
   while (nb > 4 && (total_nodes + nb - 1) / nb < 4096) nb >>= 1;
   return nb;
 }
