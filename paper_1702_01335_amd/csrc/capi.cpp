@@ -810,10 +810,12 @@ static int device_cus() {
 }
 
 // Nodes per closure block of a batch, one count for all its groups: the smallest of
-// 4, 8, ..., 64 for which every closure item of the batch (the node blocks of each group
-// plus one wall item per instance) is resident at once, so the closure launch runs in a
-// single round (its time is then one block's critical path, and fewer nodes per block
-// shorten that path).
+// 4, 8, 16 for which every closure item of the batch (the node blocks of each group plus
+// one wall item per instance) is resident at once, so the closure launch runs in a single
+// round (its time is then one block's critical path, and fewer nodes per block shorten that
+// path); 16 when none is.  Larger blocks would keep a big batch in one round, but measured
+// on single groups of 65 536 and 262 144 nodes, 16-node blocks in several rounds beat
+// 32- and 64-node blocks, whose LDS leaves fewer blocks per CU.
 static int batch_closure_nodes(hrlb_sim* const* sims, int nsims) {
   const long long ncu = device_cus();
   for (int nb = 4;; nb *= 2) {

@@ -126,7 +126,7 @@ int launch_batch_closure(int stage, const GroupDesc* groups, const void* items, 
                          size_t lds_bytes, void* stream);
 size_t stage_lds_bytes_for(int waves);
 size_t closure_lds_bytes_for(const Shape& sh, int nb);
-constexpr int CL_NODES = 64;  // most nodes per closure block
+constexpr int CL_NODES = 16;  // most nodes per closure block
 int closure_nodes_for(int total_nodes);
 int batch_closure_blocks_per_cu(size_t lds_bytes);  // resident batch-closure blocks per CU
 

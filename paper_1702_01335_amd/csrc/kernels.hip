@@ -514,8 +514,9 @@ __global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, cons
 }
 
 // ---------------------------------------------------------------------------------------
-// closure: up to 64 nodes per block (one lane per node for the scalar closure, one per node
-// and semi-axis for the half-range projections), plus one wall block per instance
+// closure: up to CL_NODES = 16 nodes per 64-lane block (one lane per node for the scalar
+// closure, one per node and semi-axis for the half-range projections, four per node and
+// moment for the partial sums), plus one wall block per instance
 
 
 // one closure work item: node block `blk` (< node_blocks) or the wall of instance
@@ -723,9 +724,8 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
   // 3) the half-range projection coefficients n J^+ and n J^-, one lane per node and
   //    semi-axis (the two share one pass through the exponential and erfc), and g_y and g_z
   //    of every node of the block
-  //    (at most 2 x 64 tasks; straight-line passes, since in a loop the compiler would hold
-  //    the constants of erfc in registers across it)
-  static_assert(CL_NODES <= 64, "two passes cover every (node, semi-axis) task");
+  //    (at most 2 x CL_NODES tasks, one pass of the block's 64 lanes)
+  static_assert(2 * CL_NODES <= 64, "one pass covers every (node, semi-axis) task");
   auto half_pair = [&](int t) {
     if (t < 2 * nblk_nodes) {
       const int nd = t >> 1;
@@ -740,7 +740,6 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
     }
   };
   half_pair(lane);
-  if (nblk_nodes > 32) half_pair(lane + 64);
   for (int idx = lane; idx < nblk_nodes * Qyz; idx += 64) {
     const int nd = idx / Qyz, e = idx - nd * Qyz;
     const double* sn = scal + nd * SC;
@@ -797,12 +796,12 @@ static inline size_t closure_lds_doubles(const Shape& sh, int nb) {
          (size_t)(sh.Nx + 1) * (sh.Nx + 1);
 }
 
-// nodes per closure block: 16, fewer when there are few nodes, so the grid keeps several
-// thousand blocks.  Timed on the benchmark batch (65 536 nodes) and on the reduced model's
-// (262 144 nodes): 16 is the fastest on both (8, 32 and 64 take 1.05-1.37x and 1.09-1.47x
-// as long; a block of 64 nodes needs 27 KB of LDS, five blocks per CU)
+// nodes per closure block: CL_NODES, fewer when there are few nodes, so the grid keeps
+// several thousand blocks.  Timed on the benchmark batch (65 536 nodes) and on the reduced
+// model's (262 144 nodes): 16 is the fastest on both (8, 32 and 64 take 1.05-1.37x and
+// 1.09-1.47x as long; a block of 64 nodes needs 27 KB of LDS, five blocks per CU)
 static inline int closure_nodes_per_block(int total_nodes) {
-  int nb = 16;
+  int nb = CL_NODES;
   while (nb > 4 && (total_nodes + nb - 1) / nb < 4096) nb >>= 1;
   return nb;
 }

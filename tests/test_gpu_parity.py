@@ -78,13 +78,12 @@ def test_batch_of_different_instances():
         assert res[b] == pytest.approx(Ro, rel=1e-9)
 
 
-def test_closure_blocks_of_64_nodes():
-    """1100 instances x 250 nodes, each instance with its own parameters: the single-instance
-    path (16-node closure blocks) matches the oracle on a sample, the last instance included.
-    The same instances as a one-group batch take 64-node closure items, so the half-range
-    projections need their second pass of (node, semi-axis) tasks; 250 is not a multiple of
-    64, so items straddle instances and the last holds 56 nodes; the node count changes no
-    sum, so the two paths agree to rounding of the residual only."""
+def test_closure_blocks_straddle_instances():
+    """1100 instances x 250 nodes, each instance with its own parameters: 250 is not a
+    multiple of the closure's 16 nodes per block, so blocks straddle instances, and the last
+    block holds 8 nodes.  A sample, the last instance included, matches the oracle; the same
+    instances as a one-group batch (its closure items take 16 nodes as well) give the same
+    populations."""
     base = make_wl(3, 4, 4, 250, 'weno5', dt=2e-4)
     B = 1100
     plist = []
@@ -99,8 +98,7 @@ def test_closure_blocks_of_64_nodes():
         Fo, m, Ro = oracle_run(base, 3, seed=4000 + b, params=plist[b])
         assert_parity(Fg[b], Fo, m, f"instance {b} of {B}")
         assert res[b] == pytest.approx(Ro, rel=1e-9)
-    # the same instances as a one-group batch: its closure items take 64 nodes (32 would need
-    # more items than blocks can be resident); same launch shape, so the same sums
+    # the same instances as a one-group batch: same launch shape, so the same sums
     import torch
     q = hrlb.Quadrature(3, 4, 4)
     r = torch.from_numpy(np.stack([inputs.perturbation(sd, (250, q.V)) for sd in seeds])).cuda()
@@ -109,7 +107,7 @@ def test_closure_blocks_of_64_nodes():
     bt.step(3)
     Fb = s.get_state().cpu().numpy()
     err = np.abs(Fb - Fg).max() / np.abs(Fg).max()
-    print(f"[parity] batched 64-node closure items: max rel diff vs single-instance path {err:.2e}", flush=True)
+    print(f"[parity] batched closure items: max rel diff vs single-instance path {err:.2e}", flush=True)
     assert err <= 1e-15
     assert np.allclose(bt.residual(), res, rtol=1e-13)
 
