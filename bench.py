@@ -109,7 +109,41 @@ def profiled_traffic(tag, bytes_per_launch, cells, waves):
         return None
     ks = tr['stage_kernels'].values()
     t = sum(k['fetch_bytes'] + k['write_bytes'] for k in ks) / len(ks)
-    return {'bytes_per_launch': t, 'over_algorithmic': t / bytes_per_launch, 'source': f'profiles/{tag}_c{cells}w{waves}.md'}
+    # counted bytes of each RK3 stage: the stage is the second template argument of the name
+    per_stage = [None, None, None]
+    for name, k in tr['stage_kernels'].items():
+        st = int(name.split('<')[1].split(',')[1])
+        per_stage[st - 1] = k['fetch_bytes'] + k['write_bytes']
+    return {'bytes_per_launch': t, 'over_algorithmic': t / bytes_per_launch, 'per_stage_bytes': per_stage,
+            'source': f'profiles/{tag}_c{cells}w{waves}.md'}
+
+
+def delivered_bandwidth(device, mib=512, reps=10):
+    """What this GPU's HBM delivers to plain streams, timed now: a device copy (one read, one
+    write stream, like the first RK3 stage) and an add (two reads, one write, like stages 2
+    and 3) of mib-MiB float64 arrays, in bytes/s."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device=device)
+    y = torch.ones_like(x)
+    z = torch.empty_like(x)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    copy = 2 * n * 8 / timed(lambda: z.copy_(x))
+    add = 3 * n * 8 / timed(lambda: torch.add(x, y, out=z))
+    del x, y, z
+    torch.cuda.empty_cache()
+    return copy, add
 
 
 def sweep_section(n_inst, n_steady, steps):
@@ -392,6 +426,16 @@ def main():
                  for k in range(3)]
     traffic = profiled_traffic(f"stage_kernel_{args.workload}_b{args.batch}", bytes_per_launch, cells, waves)
     res = solver.residual()
+    # the stages against what the same GPU gives plain streams of the same mix: the counted
+    # bytes of each stage (profiled shape and source only) over its time, against the copy
+    # (stage 1) or the add (stages 2 and 3)
+    bw_copy, bw_add = delivered_bandwidth(device)
+    if traffic:
+        for k, ps in enumerate(per_stage):
+            cb = traffic['per_stage_bytes'][k]
+            ps['counted_bytes'] = cb
+            ps['counted_GBs'] = cb / stage_s[k] / 1e9
+            ps['frac_of_delivered'] = cb / stage_s[k] / (bw_copy if k == 0 else bw_add)
 
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 8
@@ -435,6 +479,9 @@ def main():
                      'kernel': 'stage_kernel (the three RK3 stages; frac over their average launch)',
                      'avg_launch_us': stage_avg_s * 1e6, 'bytes_per_launch': bytes_per_launch,
                      'per_stage': per_stage, 'closure_avg_us': closure_avg_s * 1e6,
+                     'delivered': {'copy_GBs': bw_copy / 1e9, 'add_GBs': bw_add / 1e9,
+                                   'how': 'torch device copy (1 read + 1 write) and add (2 reads + 1 write) '
+                                          'of 512 MiB float64 arrays, timed in this run'},
                      'step_frac': pairs * BYTES_PER_PAIR_STEP / (ms * 1e-3) / HBM_PEAK},
         'single_instance': single,
         'residual_max': float(res.max()),

@@ -43,6 +43,7 @@ def test_committed_profiles_match_the_kernel_source():
         c, w = tr['launch']['cells'], tr['launch']['waves']
         t = bench.profiled_traffic(TAG, 1.0e9, c, w)
         assert t is not None and t['bytes_per_launch'] > 1.0e9, f
+        assert all(b is not None and b > 5.0e8 for b in t['per_stage_bytes']), f
         assert t['source'] == f'profiles/{TAG}_c{c}w{w}.md'
 
 
