@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 def gpu_reduced(wl, steps, seed, eps=0.05, launch=None, graph=False):
     import torch
-    q = hrlb.ReducedQuadrature(wl['Qx'], wl['Qy'])
+    q = hrlb.ReducedQuadrature(wl['Qx'], wl['Qy'], wl.get('Nx'), wl.get('Ny'))
     r = torch.from_numpy(inputs.perturbation(seed, (wl['S'], q.V))[None]).cuda()
     s = hrlb.Solver(q, wl['S'], wl['scheme'], [hrlb.make_params(**wl['params'])], perturb=r, eps=eps)
     if launch:
@@ -129,3 +129,19 @@ def test_explicit_z_sums_equal_the_reduced_model(pr):
     assert np.abs(phi - Fr[..., 0]).max() / scale < 1e-13
     assert np.abs(chi - Fr[..., 1]).max() / scale < 1e-13
     assert np.abs(se.moments().cpu().numpy()[0, :, 2]).max() > 1e-2
+
+
+def test_reduced_largest_velocity_set():
+    """The paper's largest model, HHLB(6;100) on x, with HLB(15;16) on y (2 x 200 x 16
+    populations per node), 13 nodes, 5 steps from a seeded start."""
+    wl = make_wl(100, 16, 1, 13, 'weno5', dt=1e-3, kn=1.0, u_w=0.3, omega=0.5)
+    wl.update(Nx=6, Ny=15)
+    Fg, _, _ = gpu_reduced(wl, 5, seed=77)
+    Fo, _, _ = oracle_reduced(wl, 5, seed=77)
+    err = np.abs(Fg - Fo)
+    norm = err.max() / np.abs(Fo).max()
+    col = (err.max(axis=0) / np.abs(Fo).max(axis=0)).max()
+    print(f"[reduced] HHLB(6;100) x HLB(15;16): normwise {norm:.2e}, column {col:.2e}", flush=True)
+    # per column: twice the measured 1.9e-8; the x factors of HHLB(6;100) are off the exact
+    # (mpmath) ones by up to 3.5e-9 per column on both sides, so 1e-10 is out of reach
+    assert norm <= NORM_TOL and col <= 4e-8
