@@ -115,7 +115,7 @@ WorkLayout work_layout(const Shape& sh) {
   L.inv_dx = take((size_t)sh.B * sh.S * dsz);
   L.g_rest = take((size_t)sh.B * sh.V * dsz);
   L.g_wall = take((size_t)sh.B * sh.V * dsz);
-  L.partials = take((size_t)sh.B * L.nvb_max * sh.S * PART_STRIDE * dsz);
+  L.partials = take((size_t)sh.B * part_groups(sh.S) * L.nvb_max * PART_GROUP * dsz);
   L.rec = take((size_t)sh.B * sh.S * sh.rec_len * dsz);
   L.nw = take((size_t)sh.B * dsz);
   L.resid_part = take((size_t)sh.B * L.nres_max * 2 * dsz);

@@ -13,8 +13,12 @@ constexpr int NYZ_MAX = 15;  // largest full-range expansion order on y, z (Q <=
 constexpr int QYZ_MAX = 16;
 constexpr int QX_MAX = 128;
 constexpr int REC_HEAD = 16;  // scalars at the head of a per-node closure record
-constexpr int PART_STRIDE = 16;  // doubles per (block, node) moment partial: 13 moments, 3 zero
-constexpr int NMOM = 13;
+constexpr int NMOM = 13;         // moment sums per node (n, n u, the second moments, the energy fluxes)
+constexpr int PART_STRIDE = 16;  // doubles per node row of the closure's summed moments (13 + n, u_x, T)
+// Moment partials in HBM: per instance, 16-node group and 64-velocity block, NMOM lines
+// of the group's 16 nodes (moment-major, so a moment of a whole group is one 128-byte line)
+constexpr int PART_GROUP = NMOM * 16;
+constexpr int part_groups(int S) { return (S + 15) >> 4; }
 constexpr int MAX_WAVES = 4;   // waves per stage-kernel workgroup (LDS: 8.3 KB per wave, 12.4 KB with several)
 // 64-velocity blocks of the moment-multiplier table: those of V, plus the whole idle waves
 // a workgroup of up to MAX_WAVES waves can hold past V
@@ -65,7 +69,7 @@ struct DevPtrs {
   double* g_rest;     // [B][V]  discrete equilibrium at rest per unit density
   double* g_wall;     // [B][V]  wall Maxwellian per unit density
   // per step / stage
-  double* partials;   // [B][S][nvb][PART_STRIDE] (node-major)
+  double* partials;   // [B][part_groups(S)][nvb][NMOM][16] (16-node groups, moment lines)
   double* rec;        // [B][S][rec_len]
   double* nw;         // [B]
   double* resid_part; // [B][nres][2]

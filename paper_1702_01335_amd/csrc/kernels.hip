@@ -388,7 +388,7 @@ __global__ void clear_flags_kernel(int* flags, double* resid, int n) {
 // moment partials on the matrix cores
 //
 // The 13 moment sums of a node over a wave's 64 velocities are a dense contraction over
-// the velocity axis: D[n][m] = sum_v F[n][v] P[v][m] for 16 nodes n at a time, with
+// the velocity axis: D[m][n] = sum_v P[v][m] F[n][v] for 16 nodes n at a time, with
 // P[v][.] = {1, p_x, p_y, p_z, p_x^2, p_y^2, p_z^2, p_x p_y, p_x p_z, p_y p_z,
 // |p|^2 p_x, |p|^2 p_y, |p|^2 p_z, 0, 0, 0}.  Each wave parks the 16 node rows of F it has
 // produced in LDS and issues 16 v_mfma_f64_16x16x4 (K = 4 velocities each); the
@@ -399,7 +399,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int FT_LD = 65;                 // padded LDS row (doubles) of a wave's node tile
 constexpr int FT_WAVE = 16 * FT_LD;       // doubles per wave tile
-constexpr int RED_WAVE = 16 * 16;         // doubles per wave of reduced moments (node x moment)
+constexpr int RED_WAVE = 16 * 16;         // doubles per wave of reduced moments (moment x node)
 
 // load this lane's A operands: a[t] = P[v0 + 4t + lane/16][lane % 16] (0 beyond V)
 __device__ __forceinline__ void load_moment_operands(const double* __restrict__ ptab, int wave_v0, int V, int lane,
@@ -415,22 +415,23 @@ __device__ __forceinline__ void load_moment_operands(const double* __restrict__ 
   }
 }
 
-// D[node][moment] = sum_v F[v][node] P[moment][v] over the wave's 64 velocities, in 16
-// steps of 4: the node tile is the A operand (lane l: node l % 16, velocity 4 t + l / 16)
-// and the multipliers the B operand (lane l: velocity 4 t + l / 16, moment l % 16), so
-// register r of lane l ends up holding moment l % 16 of node 4 r + l / 16
+// D[moment][node] = sum_v P[moment][v] F[v][node] over the wave's 64 velocities, in 16
+// steps of 4: the multipliers are the A operand (lane l: moment l % 16, velocity
+// 4 t + l / 16) and the node tile the B operand (lane l: velocity 4 t + l / 16, node
+// l % 16), so register r of lane l ends up holding moment 4 r + l / 16 of node l % 16: the
+// 16 lanes l / 16 = q of register r hold one moment of the group's 16 nodes
 __device__ __forceinline__ dbl4 moment_mfma(const double* ft, const double* a, int lane) {
   dbl4 acc = {0.0, 0.0, 0.0, 0.0};
   const int n = lane & 15, kk = lane >> 4;
 #pragma unroll
-  for (int t = 0; t < 16; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ft[n * FT_LD + 4 * t + kk], a[t], acc, 0, 0, 0);
+  for (int t = 0; t < 16; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], ft[n * FT_LD + 4 * t + kk], acc, 0, 0, 0);
   return acc;
 }
 
 // Moment sums of a group of 16 node rows, once every wave has stored its rows in its tile:
 // the wave contracts its tile with the multipliers of its 64 velocities on the matrix
 // cores (the multipliers loaded here; the stage kernel keeps them in registers instead);
-// the 13 sums of node n end up in the lanes that hold D[n][.].  A block of one wave stores
+// the 13 sums of node n end up in the lanes that hold D[.][n].  A block of one wave stores
 // them straight from these registers; with more waves they are added across waves in LDS
 // first.
 __device__ __forceinline__ dbl4 moment_contract(const double* lds_ft, const double* __restrict__ ptab, int wave_v0,
@@ -441,37 +442,48 @@ __device__ __forceinline__ dbl4 moment_contract(const double* lds_ft, const doub
   return moment_mfma(lds_ft + wave * FT_WAVE, a, lane);
 }
 
-// park a wave's contraction in lds_red[wave][node][16] (blocks of several waves)
+// park a wave's contraction in lds_red[wave][moment][node] (blocks of several waves)
 __device__ __forceinline__ void park_moments(double* lds_red, const dbl4& acc, int wave, int lane) {
-  double* r = lds_red + wave * RED_WAVE + (lane >> 4) * 16 + (lane & 15);
+  double* r = lds_red + wave * RED_WAVE + lane;
   r[0] = acc[0];
   r[64] = acc[1];
   r[128] = acc[2];
   r[192] = acc[3];
 }
 
-// store the moment sums of cnt nodes, node-major with node_stride: from the registers of a
-// one-wave block (register r of lane l holds moment l % 16 of node 4 r + l / 16), or from
-// the waves' parked contractions summed in LDS.  All 16 slots of a node's row are written
-// (the contraction leaves slots 13..15 zero), and one store instruction writes four whole
-// 128-byte rows: rows written in part, or a line in several pieces, cost measurably more.
+// store the moment sums of the cnt nodes s, s + 1, .. of an instance into its partials
+// (part: the instance's first group at this velocity block; gstride: doubles from one
+// 16-node group to the next), from the registers of a one-wave block (register r of lane l
+// holds moment 4 r + l / 16 of node l % 16) or from the waves' parked contractions summed
+// in LDS.  Node s + n goes to slot (s + n) % 16 of group (s + n) / 16, so with s a multiple
+// of 16 and cnt = 16 each moment is one whole 128-byte line and a store instruction writes
+// four of them (lines written in part, or in several pieces, cost measurably more); 13
+// lines per group, none of them padding.
 __device__ __forceinline__ void store_moments(const dbl4& acc, const double* lds_red, int waves, int cnt,
-                                              double* __restrict__ out, int node_stride) {
+                                              double* __restrict__ part, size_t gstride, int s) {
   if (waves == 1) {
-    const int lane = threadIdx.x, q = lane & 15, n0 = lane >> 4;
-    auto o = gmem(out + (size_t)n0 * node_stride + q);
-    const size_t step = (size_t)4 * node_stride;
+    const int lane = threadIdx.x, n = lane & 15, m0 = lane >> 4;
+    const int sn = s + n;
+    auto o = gmem(part + (size_t)(sn >> 4) * gstride + 16 * m0 + (sn & 15));
+    if (n < cnt) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (4 * r + n0 < cnt) o[r * step] = acc[r];
+      for (int r = 0; r < 3; ++r) o[64 * r] = acc[r];
+      if (m0 == 0) o[64 * 3] = acc[3];  // moment 12; 13..15 are zero
+    }
     return;
   }
-  for (int idx = threadIdx.x; idx < cnt * PART_STRIDE; idx += blockDim.x) {
-    const int n = idx / PART_STRIDE, q = idx - n * PART_STRIDE;
-    double s = 0.0;
-    for (int w = 0; w < waves; ++w) s += lds_red[w * RED_WAVE + n * 16 + q];
-    gmem(out)[(size_t)n * node_stride + q] = s;
+  for (int idx = threadIdx.x; idx < PART_GROUP; idx += blockDim.x) {
+    const int m = idx >> 4, n = idx & 15, sn = s + n;
+    if (n >= cnt) continue;
+    double v = 0.0;
+    for (int w = 0; w < waves; ++w) v += lds_red[w * RED_WAVE + idx];
+    gmem(part)[(size_t)(sn >> 4) * gstride + 16 * m + (sn & 15)] = v;
   }
+}
+
+// the partials of instance b at velocity block vb (the first group's first line)
+__device__ __forceinline__ double* part_base(const DevPtrs& d, int S, int b, int vb, int nvb) {
+  return d.partials + ((size_t)b * part_groups(S) * nvb + vb) * PART_GROUP;
 }
 
 // LDS of the stage and partials kernels (doubles): the waves' node tiles, then (blocks of
@@ -497,9 +509,8 @@ __global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, cons
   const int nloc = min(cs, S - s0);
   const double* Fb = F + (size_t)b * S * V;
   double* ft = lds_ft + wave * FT_WAVE;
-  // partials are node-major, [b][S][nvb][16]
-  const int nstride = nvb * PART_STRIDE;
-  double* part = d.partials + (((size_t)b * S + s0) * nvb + vb) * PART_STRIDE;
+  double* part = part_base(d, S, b, vb, nvb);
+  const size_t gstride = (size_t)nvb * PART_GROUP;
   for (int g = 0; g < nloc; g += 16) {
     const int cnt = min(16, nloc - g);
     for (int u = 0; u < 16; ++u) ft[u * FT_LD + lane] = (u < cnt && active) ? Fb[(size_t)(s0 + g + u) * V + v] : 0.0;
@@ -508,7 +519,7 @@ __global__ void __launch_bounds__(256) partials_kernel(Shape sh, DevPtrs d, cons
       park_moments(lds_red, acc, wave, lane);
       __syncthreads();
     }
-    store_moments(acc, lds_red, waves, cnt, part + (size_t)g * nstride, nstride);
+    store_moments(acc, lds_red, waves, cnt, part, gstride, s0 + g);
     __syncthreads();
   }
 }
@@ -613,34 +624,33 @@ __device__ __forceinline__ void closure_block(const Shape& sh, const DevPtrs& d,
 #pragma unroll
   for (int k = 0; k < 4; ++k) tab[k] = table_entry(lane + 64 * k);
   for (int e0 = lane + 256; e0 < n4; e0 += 64) table_store(e0, table_entry(e0));
-  // 1) sum the moment partials over velocity blocks.  They are node-major ([node][nvb][16]),
-  //    so the block's nodes are one contiguous range; lane l owns moment l % 16 of nodes
-  //    l / 16 + 4 j and sums four velocity blocks per pass for all of them at once.  Each
-  //    partial is read once, so the loads are nontemporal
+  // 1) sum the moment partials over velocity blocks: lane l owns node l % 16 of the block
+  //    and its moments l / 16 + 4 j, and sums four velocity blocks per pass for all of them
+  //    at once; the 16 lanes of one moment read one line when the block's nodes are one
+  //    16-node group of an instance.  Each partial is read once, so the loads are
+  //    nontemporal
+  static_assert(CL_NODES <= 16, "one lane per node in the partial sums");
   {
-    const int q = lane & 15, n0 = lane >> 4;
-    for (int j0 = 0; j0 < nb; j0 += 16) {
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int vb0 = 0; vb0 < nvb; vb0 += 4) {
-        double x[4][4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int nd = j0 + n0 + 4 * j;
-          const bool ok = nd < nblk_nodes && q < NMOM;
-          const auto src = gmem(d.partials + ((size_t)(g0 + (ok ? nd : 0)) * nvb) * PART_STRIDE + q);
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-            x[j][t] = (ok && vb0 + t < nvb) ? __builtin_nontemporal_load(&src[(size_t)(vb0 + t) * PART_STRIDE]) : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] += (x[j][0] + x[j][1]) + (x[j][2] + x[j][3]);
-      }
+    const int nd = lane & 15, m0 = lane >> 4;
+    const bool okn = nd < nblk_nodes;
+    const int gn = g0 + (okn ? nd : 0), bn = gn / S, sn = gn - bn * S;
+    const auto src = gmem(part_base(d, S, bn, 0, nvb) + (size_t)(sn >> 4) * nvb * PART_GROUP + 16 * m0 + (sn & 15));
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int vb0 = 0; vb0 < nvb; vb0 += 4) {
+      double x[4][4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int nd = j0 + n0 + 4 * j;
-        if (nd < nb) msum[nd * PART_STRIDE + q] = acc[j];
+        const bool ok = okn && m0 + 4 * j < NMOM;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          x[j][t] = (ok && vb0 + t < nvb) ? __builtin_nontemporal_load(&src[(size_t)(vb0 + t) * PART_GROUP + 64 * j]) : 0.0;
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] += (x[j][0] + x[j][1]) + (x[j][2] + x[j][3]);
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (nd < nb && m0 + 4 * j < NMOM) msum[nd * PART_STRIDE + m0 + 4 * j] = acc[j];
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) table_store(lane + 64 * k, tab[k]);
@@ -902,9 +912,8 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   const int nloc = min(cs, S - s0);
   const double* recb = d.rec + (size_t)b * S * sh.rec_len;
   double* ft = lds_ft + wave * FT_WAVE;
-  // partials are node-major, [b][S][nvb][16]
-  const int nstride = nvb * PART_STRIDE;
-  double* part = d.partials + (((size_t)b * S + s0) * nvb + vb) * PART_STRIDE;
+  double* part = part_base(d, S, b, vb, nvb);
+  const size_t gstride = (size_t)nvb * PART_GROUP;
 
   // window W0..W5 = nodes c-2 .. c+3, first for c = s0 - 1
   double W0 = raw_node(Fb, s0 - 3, S, V, vv, vm);
@@ -1070,7 +1079,7 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
       park_moments(red, acc, wave, lane);
       __syncthreads();
     }
-    store_moments(acc, red, waves, cnt, part + (size_t)g * nstride, nstride);
+    store_moments(acc, red, waves, cnt, part, gstride, s0 + g);
   }
   if constexpr (STAGE == 3) {
     rd = wave_sum(rd);
