@@ -947,6 +947,9 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   };
   typedef __attribute__((address_space(4))) const double cdouble;
   const int clast = s0 + nloc - 1;
+  // the last window row the chunk needs: the prefetches issued for nodes past the chunk's
+  // end (never computed) re-read it instead of fetching the next chunk's rows from HBM
+  const int rtop = min(clast + 3, S - 1);
   const int gx_off = REC_HEAD + i, gyz_off = REC_HEAD + 2 * Qx + jk;
   const unsigned vv8 = 8u * vv, gx8 = 8u * gx_off, gyz8 = 8u * gyz_off;
   const __amdgpu_buffer_rsrc_t r_in = raw_rsrc(Fb), r_rec = raw_rsrc(recb);
@@ -954,7 +957,7 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
   const unsigned row8 = 8u * V, rec8 = 8u * sh.rec_len;
   auto ld_far = [&](int c, Far& o) {
     // c + 3 >= 3 on the march: never a bounce-back image
-    o.raw = ld_buf_nt(r_in, vv8, row8 * min(c + 3, S - 1));
+    o.raw = ld_buf_nt(r_in, vv8, row8 * min(c + 3, rtop));
     if constexpr (STAGE != 1)
       o.fl0 = ld_buf_nt(r_l, vv8, row8 * min(c, clast));
     else
@@ -1058,8 +1061,8 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
       ld_far(c + PIPE, far[u % PIPE]);
       ld_near(c + PIPE, near[u % PIPE]);
     }
-    // Stores happen only here, once per 16 nodes: the group's results from the lane's own
-    // LDS column, then its moment sums.  Loads and stores share one counter, so a wait
+    // Stores happen only here, once per 16 nodes: the group's results from the wave's LDS
+    // tile, then its moment sums.  Loads and stores share one counter, so a wait
     // issued while a store is in flight drains everything; with the stores bunched here
     // the march starts each group with its next operands already loaded.  Blocks of several
     // waves add their contractions in LDS, in one of two buffers taken in turn, so a single
@@ -1069,9 +1072,22 @@ __device__ __forceinline__ void stage_tile(const Shape& sh, const DevPtrs& d, co
     // earliest, and a batch's arrays outgrow the last-level cache, which then keeps the
     // moment partials and node records that the closure and the next stage read (measured:
     // 5-8 % off stage and closure together).
-    if (active) {
-      auto dst = gmem(Fout + base + (size_t)(s0 + g) * V + v);
-      for (int u = 0; u < cnt; ++u) __builtin_nontemporal_store(ft[u * FT_LD + lane], &dst[(size_t)u * V]);
+    // Each store instruction writes two node rows of the wave's 64 velocities, 16 bytes (two
+    // velocities) per lane: half the store instructions of one row per instruction.  V is
+    // even (2 Qx nodes on x), so a pair that starts below V ends below V.
+    {
+      typedef double pair_t __attribute__((ext_vector_type(2)));
+      const int pl = lane & 31, h = lane >> 5, vp = wave_v0 + 2 * pl;
+      if (vp < V) {
+        auto dst = gmem(reinterpret_cast<pair_t*>(Fout + base + (size_t)(s0 + g + h) * V + vp));
+        for (int u2 = 0; 2 * u2 + h < cnt; ++u2) {
+          const int u = 2 * u2 + h;
+          pair_t x;
+          x.x = ft[u * FT_LD + 2 * pl];
+          x.y = ft[u * FT_LD + 2 * pl + 1];
+          __builtin_nontemporal_store(x, &dst[(size_t)u2 * V]);  // V pairs = two rows
+        }
+      }
     }
     acc = moment_mfma(lds_ft + wave * FT_WAVE, pa, lane);
     double* red = lds_red + ((g >> 4) & 1) * waves * RED_WAVE;
