@@ -77,8 +77,9 @@ const char* hrlb_last_error(void);
  * trace_status -- whether the library emits roctx ranges.  With HRLB_TRACE set to anything
  * but "" or "0" when the library is first used, and the roctx library
  * (librocprofiler-sdk-roctx) loadable, every call below that enqueues work pushes a range
- * named after itself ("hrlb_step", "hrlb_moments", ...), each RK3 step replayed from its
- * graph one more ("RK3 step (graph launch)"), and an eager step one per launch ("closure",
+ * named after itself ("hrlb_step", "hrlb_moments", ...), each graph launch one more ("RK3
+ * steps (graph launch)" for eight steps, "RK3 step (graph launch)" for one), and an eager
+ * step one per launch ("closure",
  * "RK3 stage 1".."3"); a rocprofv3 --marker-trace run shows them beside the kernels.  The
  * ranges cover the host-side enqueue, not the kernels' execution.  *enabled = 1 when ranges
  * are emitted, else 0.  Errors: HRLB_EINVAL for a NULL pointer.
@@ -237,10 +238,11 @@ int hrlb_autotune(hrlb_sim* sim, int probe_steps, const char* cache_path, int* b
                   double* best_ms);
 
 /*
- * Graph mode: when on, hrlb_step replays a HIP graph holding one RK3 step (its six
- * launches, captured on a private stream on first use and after a launch-shape change)
- * on the sim's stream instead of launching the kernels one by one.  Results are
- * identical to the eager path.  Timing mode uses the eager path.
+ * Graph mode: when on, hrlb_step replays HIP graphs on the sim's stream instead of
+ * launching the kernels one by one: one holding eight RK3 steps (48 launches) for each
+ * whole eight of nsteps, one holding a single step (six launches) for the rest, each
+ * captured on a private stream when first needed and again after a launch-shape change.
+ * Results are identical to the eager path.  Timing mode uses the eager path.
  */
 int hrlb_set_graph(hrlb_sim* sim, int on);
 
@@ -263,7 +265,8 @@ int hrlb_get_stage_timing(hrlb_sim* sim, double* ms, long long* launches);
  * (group, instance, velocity block, node chunk) tiles and of closure work items (one block
  * each; retired instances drop out of both tables, so blocks past the live counts return
  * at once); one RK3
- * step of the whole batch is captured as a HIP graph on first use and replayed.  Results
+ * step of the whole batch, and eight steps for runs of eight or more, are captured as HIP
+ * graphs on first use and replayed.  Results
  * are those of stepping every sim alone with the same launch shape, bit for bit.
  *
  * batch_bytes: device bytes of the batch's tables (caller-owned, 256-byte aligned).

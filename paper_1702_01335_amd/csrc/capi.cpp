@@ -63,8 +63,9 @@ struct hrlb_sim {
   bool timing;
   bool graph_on;
   hipGraphExec_t gexec;   // one captured RK3 step (valid when gexec != nullptr)
-  hipStream_t cap_stream; // private stream the step is captured on
-  int g_cells, g_waves;   // launch shape the graph was captured with
+  hipGraphExec_t gexec_k; // GRAPH_BLOCK captured steps (nullptr until a long enough run)
+  hipStream_t cap_stream; // private stream the steps are captured on
+  int g_cells, g_waves;   // launch shape the graphs were captured with
   std::vector<hipEvent_t> ev;  // pairs (start, stop), kind in ev_kind
   std::vector<int> ev_kind;
   double ms[4];          // device time of stage 1, 2, 3 launches and of closure launches
@@ -86,7 +87,8 @@ struct hrlb_batch {
   int grid_stage, grid_closure;
   size_t lds_stage, lds_closure;
   std::vector<int> active;
-  hipGraphExec_t gexec;
+  hipGraphExec_t gexec;    // one captured batched step
+  hipGraphExec_t gexec_k;  // GRAPH_BLOCK captured batched steps
   hipStream_t cap_stream;
 };
 
@@ -486,7 +488,7 @@ int hrlb_init_state(const hrlb_quad* q, int S, int scheme, const hrlb_params* pa
   s->resid_nres = 0;
   s->timing = false;
   s->graph_on = false;
-  s->gexec = nullptr;
+  s->gexec = s->gexec_k = nullptr;
   s->cap_stream = nullptr;
   s->g_cells = s->g_waves = 0;
   for (int k = 0; k < 4; ++k) {
@@ -561,6 +563,7 @@ void hrlb_sim_free(hrlb_sim* s) {
   if (!s) return;
   for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
   if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->gexec_k) (void)hipGraphExecDestroy(s->gexec_k);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
 }
@@ -600,11 +603,17 @@ static hipError_t enqueue_step(hrlb_sim* s, hipStream_t st, int part_nvb) {
   return e;
 }
 
-static hipError_t capture_step(hrlb_sim* s) {
+// Steps captured in the long graph.  Each graph launch costs the GPU an idle gap at the
+// launch boundary (8.5 us measured between replays of a one-step graph, none between the
+// kernels inside a graph), so runs of many steps replay GRAPH_BLOCK steps per launch.
+constexpr int GRAPH_BLOCK = 8;
+
+// capture `nsteps` RK3 steps of the sim's current launch shape into *out (replaced)
+static hipError_t capture_steps(hrlb_sim* s, int nsteps, hipGraphExec_t* out) {
   hipError_t e = hipSuccess;
-  if (s->gexec) {
-    (void)hipGraphExecDestroy(s->gexec);
-    s->gexec = nullptr;
+  if (*out) {
+    (void)hipGraphExecDestroy(*out);
+    *out = nullptr;
   }
   if (!s->cap_stream) e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return e;
@@ -612,15 +621,12 @@ static hipError_t capture_step(hrlb_sim* s) {
   hipGraph_t g = nullptr;
   e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  hipError_t el = enqueue_step(s, s->cap_stream, nvb);
+  hipError_t el = hipSuccess;
+  for (int k = 0; k < nsteps && el == hipSuccess; ++k) el = enqueue_step(s, s->cap_stream, nvb);
   e = hipStreamEndCapture(s->cap_stream, &g);
   if (el != hipSuccess) e = el;
-  if (e == hipSuccess) e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   if (g) (void)hipGraphDestroy(g);
-  if (e == hipSuccess) {
-    s->g_cells = s->cells;
-    s->g_waves = s->waves;
-  }
   return e;
 }
 
@@ -643,8 +649,28 @@ int hrlb_step(hrlb_sim* s, int nsteps) {
       s->resid_nres = nvb * nch;
       n = 1;
     }
-    if (n < nsteps && (!s->gexec || s->g_cells != s->cells || s->g_waves != s->waves)) {
-      hipError_t e = capture_step(s);
+    if (n < nsteps && (s->g_cells != s->cells || s->g_waves != s->waves)) {
+      // a new launch shape: both graphs are captured again when next needed
+      for (hipGraphExec_t* x : {&s->gexec, &s->gexec_k})
+        if (*x) {
+          (void)hipGraphExecDestroy(*x);
+          *x = nullptr;
+        }
+      s->g_cells = s->cells;
+      s->g_waves = s->waves;
+    }
+    if (nsteps - n >= GRAPH_BLOCK && !s->gexec_k) {
+      hipError_t e = capture_steps(s, GRAPH_BLOCK, &s->gexec_k);
+      if (e != hipSuccess) return hip_fail(e, "step: graph capture");
+    }
+    for (; nsteps - n >= GRAPH_BLOCK; n += GRAPH_BLOCK) {
+      Range r_step("RK3 steps (graph launch)");
+      hipError_t e = hipGraphLaunch(s->gexec_k, s->stream);
+      if (e != hipSuccess) return hip_fail(e, "step: graph launch");
+      s->resid_nres = nvb * nch;
+    }
+    if (n < nsteps && !s->gexec) {
+      hipError_t e = capture_steps(s, 1, &s->gexec);
       if (e != hipSuccess) return hip_fail(e, "step: graph capture");
     }
     for (; n < nsteps; ++n) {
@@ -946,7 +972,7 @@ int hrlb_batch_create(hrlb_sim* const* sims, int nsims, int cells, int waves, vo
   bt->max_tiles = mt;
   bt->max_items = mi;
   bt->nb = nb;
-  bt->gexec = nullptr;
+  bt->gexec = bt->gexec_k = nullptr;
   bt->cap_stream = nullptr;
   char* w = (char*)d_work;
   bt->d_groups = (GroupDesc*)w;
@@ -1023,18 +1049,28 @@ int hrlb_batch_step(hrlb_batch* bt, int nsteps) {
   if (nsteps < 0) return fail(HRLB_EINVAL, "batch_step: nsteps must be >= 0");
   if (nsteps == 0) return HRLB_OK;
   Range r_call("hrlb_batch_step");
-  if (!bt->gexec) {
+  // one captured step, and GRAPH_BLOCK steps per launch for long runs (as hrlb_step)
+  auto capture = [&](int k, hipGraphExec_t* out) -> hipError_t {
     hipError_t e = hipSuccess;
     if (!bt->cap_stream) e = hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking);
     hipGraph_t g = nullptr;
     if (e == hipSuccess) e = hipStreamBeginCapture(bt->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t el = batch_enqueue_step(bt, bt->cap_stream);
+      hipError_t el = hipSuccess;
+      for (int i = 0; i < k && el == hipSuccess; ++i) el = batch_enqueue_step(bt, bt->cap_stream);
       e = hipStreamEndCapture(bt->cap_stream, &g);
       if (el != hipSuccess) e = el;
     }
-    if (e == hipSuccess) e = hipGraphInstantiate(&bt->gexec, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
+    return e;
+  };
+  if (nsteps % GRAPH_BLOCK && !bt->gexec) {
+    hipError_t e = capture(1, &bt->gexec);
+    if (e != hipSuccess) return hip_fail(e, "batch_step: graph capture");
+  }
+  if (nsteps >= GRAPH_BLOCK && !bt->gexec_k) {
+    hipError_t e = capture(GRAPH_BLOCK, &bt->gexec_k);
     if (e != hipSuccess) return hip_fail(e, "batch_step: graph capture");
   }
   // a sim stepped on its own or by another batch since may hold moment partials laid out
@@ -1045,7 +1081,12 @@ int hrlb_batch_step(hrlb_batch* bt, int nsteps) {
       HIP_TRY((hipError_t)launch_partials(sm->sh, sm->d, sm->d.F[0], bt->cells, bt->waves, bt->stream),
               "batch_step: partials");
   }
-  for (int n = 0; n < nsteps; ++n) {
+  int n = 0;
+  for (; nsteps - n >= GRAPH_BLOCK; n += GRAPH_BLOCK) {
+    Range r_step("batched RK3 steps (graph launch)");
+    HIP_TRY(hipGraphLaunch(bt->gexec_k, bt->stream), "batch_step: graph launch");
+  }
+  for (; n < nsteps; ++n) {
     Range r_step("batched RK3 step (graph launch)");
     HIP_TRY(hipGraphLaunch(bt->gexec, bt->stream), "batch_step: graph launch");
   }
@@ -1097,6 +1138,7 @@ int hrlb_batch_info(const hrlb_batch* bt, int* ntiles, int* nitems, int* grid_st
 void hrlb_batch_free(hrlb_batch* bt) {
   if (!bt) return;
   if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
+  if (bt->gexec_k) (void)hipGraphExecDestroy(bt->gexec_k);
   if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
   delete bt;
 }

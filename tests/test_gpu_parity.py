@@ -233,12 +233,15 @@ def test_numeric_fault_is_reported():
 
 
 def test_graph_replay_equals_eager_bitwise():
-    """The captured RK3 step replays the same launches: results must be bitwise equal to the
-    eager path, over several replays with eager work and synchronisations in between."""
+    """The captured RK3 steps (one step per graph, and eight per graph for runs of eight or
+    more) replay the same launches: results must be bitwise equal to the eager path, over
+    several replays with eager work, a launch-shape change and synchronisations in between."""
     wl = make_wl(5, 3, 3, 13, 'weno5', A=0.9, dt=1e-4)
     _, _, _, eager = gpu_run(wl, 0, seeds=[31])
     eager.step(10)
-    Fe = eager.get_state().cpu().numpy()
+    Fe10 = eager.get_state().cpu().numpy()
+    eager.step(27)
+    Fe37 = eager.get_state().cpu().numpy()
     _, _, _, g = gpu_run(wl, 0, seeds=[31])
     g.set_graph(True)
     g.step(3)
@@ -250,8 +253,16 @@ def test_graph_replay_equals_eager_bitwise():
     g.step(4)
     g.synchronize()
     g.step(1)
-    Fg = g.get_state().cpu().numpy()
-    assert np.array_equal(Fe, Fg)
+    assert np.array_equal(Fe10, g.get_state().cpu().numpy())
+    g.step(9)           # one eight-step graph and one single step
+    g.residual()
+    c, w = g.get_launch()
+    g.set_launch(4 if c != 4 else 8, w)  # both graphs captured again for the new chunk size
+    g.step(16)
+    g.synchronize()
+    g.set_launch(c, w)
+    g.step(2)
+    assert np.array_equal(Fe37, g.get_state().cpu().numpy())
 
 
 def test_autotune_picks_a_valid_shape_and_caches_it(tmp_path):
