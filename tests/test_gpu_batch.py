@@ -39,13 +39,14 @@ def test_batch_equals_individual_groups():
     for g, (wl, nb) in enumerate(zip(GROUPS, BATCH)):
         s, _ = make_solver(wl, nb, 100 * g)
         s.set_launch(CELLS, WAVES)
-        s.step(6)
+        s.step(16)
         alone.append((s.get_state().cpu().numpy(), s.residual()))
     sims = [make_solver(wl, nb, 100 * g)[0] for g, (wl, nb) in enumerate(zip(GROUPS, BATCH))]
     bt = hrlb.Batch(sims, CELLS, WAVES)
     info = bt.info()
     assert info['tiles'] > 0 and info['closure_items'] > 0
-    bt.step(6)
+    bt.step(6)   # the one-step graph six times
+    bt.step(10)  # the eight-step graph, then the one-step graph twice
     R = bt.residual()
     off = 0
     for s, (Fa, Ra) in zip(sims, alone):
