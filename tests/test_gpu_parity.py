@@ -50,6 +50,19 @@ def test_launch_shapes_agree_with_oracle(cells, waves):
     assert_parity(Fg[0], Fo, m, f"cells={cells} waves={waves}")
 
 
+@pytest.mark.parametrize("cells", [3, 24, 40])
+@pytest.mark.parametrize("waves", [1, 2])
+def test_chunks_straddling_partial_groups_agree_with_oracle(cells, waves):
+    """Moment partials are stored per 16-node group of an instance (one line per moment); a
+    chunk that starts inside a group (24 nodes: the second chunk's first 16 nodes are nodes
+    24..39, in groups 1 and 2; 3 nodes: chunks inside one group) writes each group's lines
+    from two tiles, which the closure must sum as one."""
+    wl = make_wl(5, 3, 3, 40, 'weno5', A=0.9, dt=1e-4)
+    Fg, _, _, _ = gpu_run(wl, 3, seeds=[13], launch=(cells, waves))
+    Fo, m, _ = oracle_run(wl, 3, seed=13)
+    assert_parity(Fg[0], Fo, m, f"S=40 cells={cells} waves={waves}")
+
+
 def test_moments_match_oracle():
     wl = SMALL[0][1]
     Fg, mom, _, _ = gpu_run(wl, 4, seeds=[5])
