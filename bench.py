@@ -36,6 +36,9 @@ def parse():
     ap.add_argument('--workload', default='couette_shakhov_s256_v800')
     ap.add_argument('--cells', type=int, default=0)
     ap.add_argument('--waves', type=int, default=0)
+    ap.add_argument('--scheme', default=None, choices=('weno5', 'linear5', 'upwind2'),
+                    help="x advection scheme instead of the workload's (to time what the scheme costs; the "
+                         "profiled byte counts then do not apply)")
     ap.add_argument('--no-cpu', action='store_true')
     ap.add_argument('--eager', action='store_true', help='launch kernels one by one instead of replaying a HIP graph')
     ap.add_argument('--no-tune', action='store_true', help='keep the default launch shape instead of autotuning it')
@@ -391,6 +394,9 @@ def main():
     import torch
     from paper_1702_01335_amd.workloads import workload
     wl = workload(args.workload)
+    own_scheme = args.scheme is None or args.scheme == wl['scheme']
+    if args.scheme:
+        wl['scheme'] = args.scheme
     device = 'cuda:0'
     torch.cuda.set_device(0)
     q, solver = make_solver(wl, args.batch, device)
@@ -424,7 +430,8 @@ def main():
     per_stage = [dict(stage=k + 1, avg_launch_us=stage_s[k] * 1e6, bytes_per_launch=stage_bytes[k],
                       achieved=stage_bytes[k] / stage_s[k] / 1e9, frac=stage_bytes[k] / stage_s[k] / HBM_PEAK)
                  for k in range(3)]
-    traffic = profiled_traffic(f"stage_kernel_{args.workload}_b{args.batch}", bytes_per_launch, cells, waves)
+    traffic = (profiled_traffic(f"stage_kernel_{args.workload}_b{args.batch}", bytes_per_launch, cells, waves)
+               if own_scheme else None)
     res = solver.residual()
     # the stages against what the same GPU gives plain streams of the same mix: the counted
     # bytes of each stage (profiled shape and source only) over its time, against the copy
